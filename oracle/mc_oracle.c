@@ -1,0 +1,369 @@
+/*
+ * CPU oracle for the bosonic multiconfigurational operators of
+ * Andriati & Gammal, "Hashing algorithms, optimized mappings and massive
+ * parallelization of multiconfigurational methods for bosons"
+ * (arXiv:2005.13679).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library may link, load or
+ * call this file; only the test-suite, the smoke check and the benchmark's
+ * CPU-baseline leg use it.  It shares no code with the GPU library.
+ *
+ * Deliberately plain and slow:
+ *   - N_c(n, m) is recomputed from its binomial definition on every use;
+ *   - configuration -> index is Algorithm 1 executed particle by particle;
+ *   - index -> configuration is Algorithm 2 executed particle by particle;
+ *   - H.C and the density matrices are obtained by applying creation and
+ *     annihilation operators to occupation vectors, one operator at a time,
+ *     with no jump tables and no case table;
+ *   - every reduction uses Neumaier-compensated summation.
+ * Rows (or density-matrix elements) are distributed over OpenMP threads; each
+ * thread owns its outputs, so results do not depend on the thread count.
+ *
+ * Complex arrays are interleaved (re, im) doubles.  h is h[k*M + l],
+ * g is g[((k*M + s)*M + q)*M + l]; rho1 and rho2 use the same layouts.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_MAXM 64
+
+/* ---------------------------------------------------------------------- */
+/* Eq. (nc): N_c(n, m) = (n + m - 1)! / (n! (m - 1)!), with N_c(n, 0) = 0   */
+/* (Eq. TotalCost).  Returns -1 if the value does not fit in int64.         */
+/* ---------------------------------------------------------------------- */
+int64_t orc_nc(int64_t n, int64_t m)
+{
+    if (m <= 0 || n < 0) return 0;
+    int64_t a = n + m - 1;          /* C(a, b) with b = m - 1 */
+    int64_t b = m - 1;
+    if (b > a - b) b = a - b;
+    unsigned __int128 r = 1;
+    for (int64_t i = 1; i <= b; ++i) {
+        r = r * (unsigned __int128)(a - b + i) / (unsigned __int128)i;
+        if (r > (unsigned __int128)INT64_MAX) return -1;
+    }
+    return (int64_t)r;
+}
+
+/* Algorithm 1: occupation vector -> index.  Orbitals are scanned from M-1
+ * down to 1; each particle found adds the cost N_c(s, m) of the particles
+ * still in the basket, and the basket loses one particle. */
+int64_t orc_hash(int32_t N, int32_t M, const int32_t *n)
+{
+    int64_t k = 0;
+    int64_t s = N;
+    for (int32_t m = M - 1; m >= 1; --m) {
+        int32_t j = n[m];
+        while (j > 0) {
+            k += orc_nc(s, m);
+            s -= 1;
+            j -= 1;
+        }
+    }
+    return k;
+}
+
+/* Algorithm 2: index -> occupation vector, by greedy descent from orbital
+ * M-1; particles left in the basket go to orbital 0.  Returns 0 on success,
+ * -1 if beta is outside [0, N_c(N, M)). */
+int orc_unhash(int32_t N, int32_t M, int64_t beta, int32_t *n)
+{
+    if (beta < 0 || beta >= orc_nc(N, M)) return -1;
+    for (int32_t i = 0; i < M; ++i) n[i] = 0;
+    int64_t k = beta;
+    int32_t m = M - 1;
+    int64_t s = N;
+    while (k > 0) {
+        while (k - orc_nc(s, m) < 0) m -= 1;
+        k -= orc_nc(s, m);
+        n[m] += 1;
+        s -= 1;
+    }
+    if (s > 0) n[0] += (int32_t)s;
+    return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Operator algebra on occupation vectors.                                  */
+/* a_j |..n_j..>  = sqrt(n_j)   |..n_j - 1..>   (zero if n_j = 0)          */
+/* a+_j|..n_j..>  = sqrt(n_j+1) |..n_j + 1..>                               */
+/* The amplitude is returned as the product of the integers under the       */
+/* square roots (exact in double for the sizes used), or 0 if the string    */
+/* annihilates the state.                                                   */
+/* ---------------------------------------------------------------------- */
+static double annihilate(int32_t *n, int32_t j)
+{
+    if (n[j] == 0) return 0.0;
+    double f = (double)n[j];
+    n[j] -= 1;
+    return f;
+}
+
+static double create(int32_t *n, int32_t j)
+{
+    n[j] += 1;
+    return (double)n[j];
+}
+
+/* Neumaier compensated accumulator */
+typedef struct { double sum, comp; } nsum;
+
+static void nadd(nsum *a, double x)
+{
+    double t = a->sum + x;
+    if (fabs(a->sum) >= fabs(x)) a->comp += (a->sum - t) + x;
+    else                          a->comp += (x - t) + a->sum;
+    a->sum = t;
+}
+
+static double nval(const nsum *a) { return a->sum + a->comp; }
+
+/* H.C for a list of rows, by operator algebra (Eq. Haction with the
+ * Hamiltonian of Sec. II).  For output row gamma,
+ *   (H C)_gamma = sum_beta <gamma|H|beta> C_beta,
+ * and each nonzero <gamma|O|beta> is found by applying O^dagger to |gamma>:
+ *   O = a+_k a_l                -> O^dagger = a+_l a_k
+ *   O = a+_k a+_s a_q a_l       -> O^dagger = a+_l a+_q a_s a_k
+ * (operators applied right to left).  All M^2 and M^4 index tuples are
+ * visited; tuples whose coefficient is exactly zero are skipped. */
+void orc_apply_h_rows(int32_t N, int32_t M, const double *h, const double *g,
+                      const double *C, const int64_t *rows, int64_t nrows,
+                      double *out)
+{
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t r = 0; r < nrows; ++r) {
+        int32_t n0[ORC_MAXM], n[ORC_MAXM];
+        int64_t gamma = rows[r];
+        orc_unhash(N, M, gamma, n0);
+        nsum re = {0, 0}, im = {0, 0};
+        /* one-body part */
+        for (int32_t k = 0; k < M; ++k) {
+            for (int32_t l = 0; l < M; ++l) {
+                double hr = h[2 * (k * M + l)], hi = h[2 * (k * M + l) + 1];
+                if (hr == 0.0 && hi == 0.0) continue;
+                memcpy(n, n0, sizeof(int32_t) * M);
+                double amp2 = annihilate(n, k);
+                if (amp2 == 0.0) continue;
+                amp2 *= create(n, l);
+                double amp = sqrt(amp2);
+                int64_t beta = orc_hash(N, M, n);
+                double cr = C[2 * beta], ci = C[2 * beta + 1];
+                nadd(&re, amp * (hr * cr - hi * ci));
+                nadd(&im, amp * (hr * ci + hi * cr));
+            }
+        }
+        /* two-body part, with the factor 1/2 of the interaction operator */
+        for (int32_t k = 0; k < M; ++k)
+        for (int32_t s = 0; s < M; ++s)
+        for (int32_t q = 0; q < M; ++q)
+        for (int32_t l = 0; l < M; ++l) {
+            size_t gi = (((size_t)k * M + s) * M + q) * M + l;
+            double gr = g[2 * gi], gim = g[2 * gi + 1];
+            if (gr == 0.0 && gim == 0.0) continue;
+            memcpy(n, n0, sizeof(int32_t) * M);
+            double amp2 = annihilate(n, k);
+            if (amp2 == 0.0) continue;
+            double f = annihilate(n, s);
+            if (f == 0.0) continue;
+            amp2 *= f;
+            amp2 *= create(n, q);
+            amp2 *= create(n, l);
+            double amp = 0.5 * sqrt(amp2);
+            int64_t beta = orc_hash(N, M, n);
+            double cr = C[2 * beta], ci = C[2 * beta + 1];
+            nadd(&re, amp * (gr * cr - gim * ci));
+            nadd(&im, amp * (gr * ci + gim * cr));
+        }
+        out[2 * r] = nval(&re);
+        out[2 * r + 1] = nval(&im);
+    }
+}
+
+/* One element of the one-body density matrix, Eq. (rho1):
+ *   rho_kl = sum_gamma conj(C_gamma) <gamma|a+_k a_l|beta> C_beta. */
+static void rho1_element(int32_t N, int32_t M, int64_t D, const double *C,
+                         int32_t k, int32_t l, double *out)
+{
+    nsum re = {0, 0}, im = {0, 0};
+    int32_t n[ORC_MAXM];
+    for (int64_t gamma = 0; gamma < D; ++gamma) {
+        orc_unhash(N, M, gamma, n);
+        double amp2 = annihilate(n, k);
+        if (amp2 == 0.0) continue;
+        amp2 *= create(n, l);
+        double amp = sqrt(amp2);
+        int64_t beta = orc_hash(N, M, n);
+        double ar = C[2 * gamma], ai = -C[2 * gamma + 1];
+        double br = C[2 * beta], bi = C[2 * beta + 1];
+        nadd(&re, amp * (ar * br - ai * bi));
+        nadd(&im, amp * (ar * bi + ai * br));
+    }
+    out[0] = nval(&re);
+    out[1] = nval(&im);
+}
+
+void orc_rho1(int32_t N, int32_t M, const double *C, double *rho1)
+{
+    int64_t D = orc_nc(N, M);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t e = 0; e < M * M; ++e)
+        rho1_element(N, M, D, C, e / M, e % M, rho1 + 2 * e);
+}
+
+/* One element of the two-body density matrix, Eq. (rho2):
+ *   rho_ksql = sum_gamma conj(C_gamma) <gamma|a+_k a+_s a_q a_l|beta> C_beta. */
+static void rho2_element(int32_t N, int32_t M, int64_t D, const double *C,
+                         int32_t k, int32_t s, int32_t q, int32_t l,
+                         double *out)
+{
+    nsum re = {0, 0}, im = {0, 0};
+    int32_t n[ORC_MAXM];
+    for (int64_t gamma = 0; gamma < D; ++gamma) {
+        orc_unhash(N, M, gamma, n);
+        double amp2 = annihilate(n, k);
+        if (amp2 == 0.0) continue;
+        double f = annihilate(n, s);
+        if (f == 0.0) continue;
+        amp2 *= f;
+        amp2 *= create(n, q);
+        amp2 *= create(n, l);
+        double amp = sqrt(amp2);
+        int64_t beta = orc_hash(N, M, n);
+        double ar = C[2 * gamma], ai = -C[2 * gamma + 1];
+        double br = C[2 * beta], bi = C[2 * beta + 1];
+        nadd(&re, amp * (ar * br - ai * bi));
+        nadd(&im, amp * (ar * bi + ai * br));
+    }
+    out[0] = nval(&re);
+    out[1] = nval(&im);
+}
+
+/* Selected elements of rho2: idx[e] = ((k*M + s)*M + q)*M + l. */
+void orc_rho2_elements(int32_t N, int32_t M, const double *C,
+                       const int64_t *idx, int64_t count, double *out)
+{
+    int64_t D = orc_nc(N, M);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t e = 0; e < count; ++e) {
+        int64_t t = idx[e];
+        int32_t l = (int32_t)(t % M); t /= M;
+        int32_t q = (int32_t)(t % M); t /= M;
+        int32_t s = (int32_t)(t % M); t /= M;
+        int32_t k = (int32_t)t;
+        rho2_element(N, M, D, C, k, s, q, l, out + 2 * e);
+    }
+}
+
+void orc_rho2(int32_t N, int32_t M, const double *C, double *rho2)
+{
+    int64_t D = orc_nc(N, M);
+    int64_t total = (int64_t)M * M * M * M;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t e = 0; e < total; ++e) {
+        int64_t t = e;
+        int32_t l = (int32_t)(t % M); t /= M;
+        int32_t q = (int32_t)(t % M); t /= M;
+        int32_t s = (int32_t)(t % M); t /= M;
+        int32_t k = (int32_t)t;
+        rho2_element(N, M, D, C, k, s, q, l, rho2 + 2 * e);
+    }
+}
+
+/* Occupation vectors of a list of rows (the "hashing table" rows). */
+void orc_occ_rows(int32_t N, int32_t M, const int64_t *rows, int64_t nrows,
+                  int32_t *occ)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < nrows; ++r)
+        orc_unhash(N, M, rows[r], occ + r * M);
+}
+
+/* Single-jump map (Sec. IV): T1[gamma][k][l] = index of the configuration
+ * obtained by moving one particle from orbital k to orbital l, or -1 when
+ * orbital k is empty.  For k = l the configuration is unchanged. */
+void orc_t1_rows(int32_t N, int32_t M, const int64_t *rows, int64_t nrows,
+                 int32_t *t1)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < nrows; ++r) {
+        int32_t n0[ORC_MAXM], n[ORC_MAXM];
+        orc_unhash(N, M, rows[r], n0);
+        for (int32_t k = 0; k < M; ++k)
+            for (int32_t l = 0; l < M; ++l) {
+                int32_t *dst = t1 + (r * M + k) * M + l;
+                if (n0[k] == 0) { *dst = -1; continue; }
+                memcpy(n, n0, sizeof(int32_t) * M);
+                n[k] -= 1;
+                n[l] += 1;
+                *dst = (int32_t)orc_hash(N, M, n);
+            }
+    }
+}
+
+/* Number of valid removal pairs of one configuration (Sec. IV, double-jump
+ * map): pairs (k, s) with k <= s, where k = s needs n_k >= 2 and k < s needs
+ * n_k >= 1 and n_s >= 1. */
+static int64_t removal_pairs(int32_t M, const int32_t *n)
+{
+    int64_t p = 0;
+    for (int32_t k = 0; k < M; ++k)
+        for (int32_t s = k; s < M; ++s) {
+            if (k == s) { if (n[k] >= 2) ++p; }
+            else if (n[k] >= 1 && n[s] >= 1) ++p;
+        }
+    return p;
+}
+
+/* Row lengths of the double-jump map: M^2 entries per valid removal pair. */
+void orc_t2_row_lengths(int32_t N, int32_t M, const int64_t *rows,
+                        int64_t nrows, int64_t *len)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < nrows; ++r) {
+        int32_t n[ORC_MAXM];
+        orc_unhash(N, M, rows[r], n);
+        len[r] = removal_pairs(M, n) * (int64_t)M * M;
+    }
+}
+
+/* Double-jump map rows in the paper's layout (Sec. IV): for each valid
+ * removal pair (k, s), k <= s, taken in lexicographic order, a stride of M^2
+ * entries; entry q*M + l of the stride is the index of the configuration with
+ * one particle removed from k and one from s, then one added to q and one to
+ * l.  `offsets[r]` gives where row r starts in `t2` (the caller computes it
+ * from orc_t2_row_lengths). */
+void orc_t2_rows(int32_t N, int32_t M, const int64_t *rows, int64_t nrows,
+                 const int64_t *offsets, int32_t *t2)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < nrows; ++r) {
+        int32_t n0[ORC_MAXM], n[ORC_MAXM];
+        orc_unhash(N, M, rows[r], n0);
+        int32_t *dst = t2 + offsets[r];
+        for (int32_t k = 0; k < M; ++k)
+            for (int32_t s = k; s < M; ++s) {
+                int valid = (k == s) ? (n0[k] >= 2) : (n0[k] >= 1 && n0[s] >= 1);
+                if (!valid) continue;
+                for (int32_t q = 0; q < M; ++q)
+                    for (int32_t l = 0; l < M; ++l) {
+                        memcpy(n, n0, sizeof(int32_t) * M);
+                        n[k] -= 1;
+                        n[s] -= 1;
+                        n[q] += 1;
+                        n[l] += 1;
+                        *dst++ = (int32_t)orc_hash(N, M, n);
+                    }
+            }
+    }
+}
+
+/* Hash a list of occupation vectors with Algorithm 1. */
+void orc_hash_rows(int32_t N, int32_t M, const int32_t *occ, int64_t nrows,
+                   int64_t *idx)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < nrows; ++r)
+        idx[r] = orc_hash(N, M, occ + r * M);
+}
