@@ -1,0 +1,204 @@
+"""Throughput of the bosonic H.C apply on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large_random|small_random]
+
+A step is one H.C apply (Eq. Haction) through the jump maps on the workload
+N = 200 bosons, M = 5 orbitals (dim 70,058,751), complex128 coefficients;
+inputs and tables are resident in HBM before timing starts.  Prints one JSON
+line with applies/s, the HBM roofline of the apply kernel (algorithmic bytes
+per apply / mean kernel time from HIP events on the launch stream) and the
+CPU oracle timed on a bounded sample of rows on this host.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOADS = {
+    "large_random": dict(N=200, M=5, seed=2),
+    "small_random": dict(N=10, M=5, seed=0),
+}
+
+
+def algorithmic_bytes(N: int, M: int) -> dict:
+    """Bytes the table-driven apply must move, each structure once: dense
+    single-jump map (M^2 D int32), compact double-jump rows (M^2 * M(M+1)/2 *
+    N_c(N-2, M) int32), per-row offsets (D+1 int64), occupations (M D uint8),
+    coefficients in and out (16 D each)."""
+    D = math.comb(N + M - 1, N)
+    t2 = M * M * (M * (M + 1) // 2) * (math.comb(N - 2 + M - 1, N - 2) if N >= 2 else 0)
+    parts = {
+        "t1": 4 * M * M * D,
+        "t2": 4 * t2,
+        "offsets": 8 * (D + 1),
+        "occupations": M * D * (1 if N <= 255 else 2),
+        "coefficients_in": 16 * D,
+        "coefficients_out": 16 * D,
+    }
+    parts["total"] = sum(parts.values())
+    return parts
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("mc_ops.hip", "mc_internal.h"):
+        with open(os.path.join(ROOT, "paper_2005_13679_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(N: int, M: int):
+    """HBM bytes per apply from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"k_apply_N{N}_M{M}_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(N, M, h, g, C, budget_s: float = 15.0) -> dict:
+    """The oracle (plain C, OpenMP over rows) on a seeded sample of rows, scaled
+    to whole applies per second."""
+    from oracle import native
+    native.build(force=False)
+    D = C.size
+    rng = np.random.default_rng(12345)
+    pilot = rng.integers(0, D, 2000)
+    t0 = time.perf_counter()
+    native.apply_h(N, M, h, g, C, pilot)
+    rate = len(pilot) / (time.perf_counter() - t0)
+    n = int(min(D, max(2000, rate * budget_s)))
+    rows = rng.integers(0, D, n)
+    t0 = time.perf_counter()
+    native.apply_h(N, M, h, g, C, rows)
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": (n / dt) / D,
+        "unit": "applies/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"{n} seeded random rows of the {D}-row apply in {dt:.1f} s "
+                  f"({n / dt:.0f} rows/s), scaled by rows",
+    }
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="large_random", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--extras", action="store_true", help="also time rho1/rho2 passes")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
+              "path is a design, not a build", file=sys.stderr)
+        return 2
+
+    import torch
+    import paper_2005_13679_amd as mc
+    import workloads as W
+
+    wl = WORKLOADS[args.workload]
+    N, M, seed = wl["N"], wl["M"], wl["seed"]
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    print(f"[bench] workload {args.workload} N={N} M={M}: drawing inputs", file=sys.stderr, flush=True)
+    C, h, g = W.random_instance(N, M, seed)
+    D = C.size
+    t0 = time.perf_counter()
+    tab = mc.build_tables(N, M, dev)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    print(f"[bench] tables built in {build_s:.2f} s ({sum(tab.nbytes().values()) / 1e9:.2f} GB)",
+          file=sys.stderr, flush=True)
+    Cd = torch.from_numpy(C).to(dev)
+    hd = torch.from_numpy(h).to(dev)
+    gd = torch.from_numpy(g).to(dev)
+    HC = torch.empty_like(Cd)
+
+    for _ in range(args.warmup):
+        mc.apply_H(hd, gd, Cd, tab, out=HC)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(args.steps):
+        mc.apply_H(hd, gd, Cd, tab, out=HC)
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / args.steps
+    print(f"[bench] {args.steps} applies: {ms:.3f} ms each", file=sys.stderr, flush=True)
+
+    B = algorithmic_bytes(N, M)
+    achieved = B["total"] / (ms * 1e-3) / 1e9
+    traffic = measured_traffic(N, M)
+    out = {
+        "metric": "H.C applies/s (N=200, M=5, complex128) with HBM GB/s",
+        "value": 1e3 / ms,
+        "unit": "applies/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: N={N} bosons, M={M} orbitals, dim {D}, "
+                               "complex128 C, random Hermitian h, symmetric g",
+                   "N": N, "M": M, "dim": D, "parallelism": "single GPU"},
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+        },
+        "algorithmic_bytes_per_apply": B["total"],
+        "table_build_s": build_s,
+        "table_bytes": tab.nbytes(),
+    }
+
+    if args.extras:
+        extras = {}
+        for name, fn in (("rho1", lambda: mc.rho1(Cd, tab)), ("rho2", lambda: mc.rho2(Cd, tab))):
+            fn()
+            torch.cuda.synchronize()
+            s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s.record(stream)
+            fn()
+            e.record(stream)
+            torch.cuda.synchronize()
+            extras[f"{name}_ms"] = s.elapsed_time(e)
+        out["extras"] = extras
+
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a row sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(N, M, h, g, C)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

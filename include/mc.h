@@ -1,0 +1,215 @@
+/*
+ * mc.h -- C ABI of the MI355X (gfx950) library for bosonic
+ * multiconfigurational operators: Fock-space hashing, single/double jump
+ * maps, the many-body Hamiltonian apply H.C and the one/two-body reduced
+ * density matrices, after Andriati & Gammal, arXiv:2005.13679.
+ *
+ * Operator conventions (paper, Sec. II):
+ *   H = sum_{k,l} h_kl a+_k a_l + 1/2 sum_{k,s,q,l} g_ksql a+_k a+_s a_q a_l
+ *   rho1_kl   = <Psi| a+_k a_l |Psi>                         (Eq. rho1)
+ *   rho2_ksql = <Psi| a+_k a+_s a_q a_l |Psi>                (Eq. rho2)
+ * Orbitals are 0..M-1, configurations are indexed 0..D-1 with
+ * D = N_c(N, M) = C(N+M-1, N) (Eq. nc).  Index 0 is [N,0,...,0] and D-1 is
+ * [0,...,0,N]: orbital M-1 is the most significant (Algorithms 1 and 2).
+ *
+ * General rules for every call:
+ *   - Every function returns an int status (MC_OK = 0, negative on error)
+ *     unless stated otherwise.  Nothing aborts, throws or prints.
+ *   - The caller owns every buffer.  Pointers named *_d are device pointers
+ *     (HIP device memory of the current device); all others are host.
+ *   - Complex numbers are interleaved (re, im) doubles, i.e. complex128 /
+ *     hipDoubleComplex.  Matrices are row-major: h[k*M + l],
+ *     g[((k*M + s)*M + q)*M + l]; rho1 and rho2 use the same layouts.
+ *   - Device work is enqueued asynchronously on `stream` (a hipStream_t;
+ *     NULL = the null stream).  Argument errors are reported before anything
+ *     is enqueued; launch errors return MC_EHIP with the HIP code available
+ *     from mc_last_hip_error().  Faults inside kernels surface at the next
+ *     synchronising call, as with any HIP work.
+ *   - Sizes: 1 <= M <= MC_MAX_M, 1 <= N <= MC_MAX_N, and every call that
+ *     uses jump tables needs D < 2^31 (int32 table entries).
+ */
+#ifndef MC_H
+#define MC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MC_OK       0
+#define MC_EINVAL  -1   /* bad argument: N, M, null pointer, occupation sum != N, aliasing */
+#define MC_ERANGE  -2   /* index outside [0, D), dimension or table size overflow */
+#define MC_ENOMEM  -3   /* a caller buffer or workspace is too small */
+#define MC_EHIP    -4   /* a HIP call failed; see mc_last_hip_error() */
+
+#define MC_MAX_M    32
+#define MC_MAX_N    65535
+#define MC_TILE     64  /* rows per tile: one wavefront lane per row */
+
+typedef void *mc_stream;   /* hipStream_t */
+
+/* Human-readable text for a status code (static storage). */
+const char *mc_strerror(int status);
+
+/* The last hipError_t value returned to the library on the calling thread
+ * (0 if none).  Reading it does not clear it. */
+int mc_last_hip_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* Combinatorics (host only, no device work)                                */
+/* ------------------------------------------------------------------------ */
+
+/* Dimension N_c(N, M) = (N+M-1)! / (N! (M-1)!)  (Eq. nc).
+ * Returns D >= 1, or MC_EINVAL for N < 0 or M < 1, or MC_ERANGE if D does
+ * not fit in int64. */
+int64_t mc_dim(int32_t N, int32_t M);
+
+/* Configuration -> index: the perfect hash of Eq. (TotalCost) / Algorithm 1.
+ * occ[M] holds the occupations (each >= 0, sum == N).  Writes *index.
+ * MC_EINVAL on a bad occupation vector or null pointer. */
+int mc_hash(int32_t N, int32_t M, const int32_t *occ, int64_t *index);
+
+/* Index -> configuration (Algorithm 2).  Writes occ[M].
+ * MC_ERANGE if index is outside [0, D). */
+int mc_unhash(int32_t N, int32_t M, int64_t index, int32_t *occ);
+
+/* ------------------------------------------------------------------------ */
+/* Tables: the hashing table and the single/double jump maps (Secs. III-IV) */
+/* ------------------------------------------------------------------------ */
+/*
+ * All tables are stored in 64-row tiles: tile t covers rows 64t .. 64t+63,
+ * row r of the tile sits in wavefront lane r, and rows >= D are padding.
+ *
+ *   binom   int64 [N+3][M+1]        binom[x][m] = C(x+m, m)
+ *   occ     [tiles][M][64]          occupation n_m of row 64t+lane; uint8 if
+ *                                   N <= 255 else uint16 (the "hashing table")
+ *   t1      int32 [tiles][M][M][64] single-jump map: index after moving one
+ *                                   particle k -> l, -1 if n_k = 0; k = l
+ *                                   gives the row itself (n_k >= 1)
+ *   pmask   uint64 [tiles][W]       bit p set if any row of the tile has
+ *                                   removal pair p valid; W = ceil(P/64),
+ *                                   P = M(M+1)/2 pairs (k <= s) in
+ *                                   lexicographic order
+ *   t2_off  int64 [tiles+1]         start of each tile in t2 (entries)
+ *   t2      int32 [t2_off[tiles]]   double-jump map.  For each removal pair
+ *                                   p with its pmask bit set, in increasing
+ *                                   p, a block of M*M*64 entries:
+ *                                   entry (q*M + l)*64 + lane is the index
+ *                                   after removing one particle from k and
+ *                                   one from s and adding one to q and one
+ *                                   to l, or -1 if the pair is not valid
+ *                                   for that row (k = s needs n_k >= 2,
+ *                                   k < s needs n_k >= 1 and n_s >= 1).
+ *
+ * The double-jump content is exactly the paper's variable-length rows
+ * (Sec. IV, Fig. jump_illustration): per row, a stride of M^2 entries per
+ * valid removal pair in lexicographic order, slot q*M + l.  Only the memory
+ * order differs: tiles are stored slot-major so that 64 consecutive rows
+ * read 64 consecutive entries.
+ */
+typedef struct mc_table_sizes {
+    int64_t dim;            /* D */
+    int64_t tiles;          /* ceil(D / 64) */
+    int32_t occ_bytes;      /* bytes per occupation: 1 or 2 */
+    int32_t pair_words;     /* W */
+    int64_t binom_bytes;
+    int64_t occ_bytes_total;
+    int64_t t1_bytes;
+    int64_t pmask_bytes;
+    int64_t t2_off_bytes;
+    int64_t t2_compact_entries; /* entries of the paper's packed rows:
+                                   M^2 * M(M+1)/2 * N_c(N-2, M) */
+} mc_table_sizes;
+
+/* Sizes of every table for (N, M).  Host only.  MC_ERANGE if D >= 2^31. */
+int mc_tables_size(int32_t N, int32_t M, mc_table_sizes *out);
+
+typedef struct mc_tables {
+    int32_t N, M;
+    int64_t dim, tiles;
+    int64_t *binom_d;
+    void *occ_d;
+    int32_t *t1_d;
+    uint64_t *pmask_d;
+    int64_t *t2_off_d;
+    int32_t *t2_d;           /* may be NULL until mc_build_double_jumps */
+    int64_t t2_entries;      /* capacity of t2_d, in entries */
+    int64_t t2_required;     /* set by mc_build_jump_tables */
+} mc_tables;
+
+/* Builds binom, occ, t1, pmask and t2_off into the caller's buffers (sizes
+ * from mc_tables_size; t->N, t->M must match).  Synchronises `stream` once
+ * at the end to read t2_off[tiles] into t->t2_required (entries the double
+ * jump map needs).  MC_EINVAL on a missing buffer or mismatched N/M. */
+int mc_build_jump_tables(int32_t N, int32_t M, mc_tables *t, mc_stream stream);
+
+/* Fills t->t2_d.  Needs a completed mc_build_jump_tables on the same tables
+ * and t->t2_entries >= t->t2_required (else MC_ENOMEM). */
+int mc_build_double_jumps(int32_t N, int32_t M, const mc_tables *t, mc_stream stream);
+
+/* Device-side hash / unhash of many configurations, row-major int32
+ * occupations occ_d[count][M].  The binomial table comes from built tables
+ * (only t->binom_d is read).  Invalid rows produce -1 (hash) or a row of -1
+ * (unhash); nothing faults. */
+int mc_hash_batch(int32_t N, int32_t M, const mc_tables *t, const int32_t *occ_d,
+                  int64_t *index_d, int64_t count, mc_stream stream);
+int mc_unhash_batch(int32_t N, int32_t M, const mc_tables *t, const int64_t *index_d,
+                    int32_t *occ_d, int64_t count, mc_stream stream);
+
+/* Reads the double-jump map entry for (row, k, s, q, l) of each query
+ * (queries_d[count][5] int64: row, k, s, q, l with any k, s order) into
+ * out_d[count]; -1 where the removal is not possible.  A test and debugging
+ * accessor for the tiled layout. */
+int mc_t2_lookup(int32_t N, int32_t M, const mc_tables *t, const int64_t *queries_d,
+                 int32_t *out_d, int64_t count, mc_stream stream);
+
+/* ------------------------------------------------------------------------ */
+/* Operators                                                                */
+/* ------------------------------------------------------------------------ */
+
+#define MC_OP_APPLY 1
+#define MC_OP_RHO1  2
+#define MC_OP_RHO2  3
+#define MC_OP_DOT   4
+
+/* Bytes of device workspace `op` needs for (N, M) (0 is possible). */
+int mc_workspace_size(int32_t N, int32_t M, int32_t op, size_t *bytes);
+
+/* HC_d = H . C_d  (Eq. Haction), matrix-free through the jump maps:
+ *   (H C)_g = sum_k h_kk n_k C_g
+ *           + sum_{k != l, n_k >= 1} h_kl sqrt(n_k (n_l+1)) C[t1[g][k][l]]
+ *           + 1/2 sum_{valid pairs k<=s} A_ks sum_{q,l} G'_{ks,ql} B_ql C[t2 slot]
+ * with G'_{ks,ql} = g_ksql + g_skql (k < s), g_kkql (k = s),
+ * A_ks = sqrt(n_k n_s) or sqrt(n_k(n_k-1)), and B_ql the creation amplitudes
+ * on m = n - e_k - e_s (sqrt((m_q+1)(m_l+1)), or sqrt((m_q+1)(m_q+2)) if
+ * q = l).  h_d [M*M], g_d [M^4], C_d and HC_d [D] complex128 on the device;
+ * HC_d must not overlap C_d (MC_EINVAL).  ws_d: mc_workspace_size(APPLY).
+ * No symmetry of h or g is assumed. */
+int mc_apply_H(int32_t N, int32_t M, const double *h_d, const double *g_d,
+               const mc_tables *t, const double *C_d, double *HC_d,
+               void *ws_d, size_t ws_bytes, mc_stream stream);
+
+/* rho1_d [M*M] = <a+_k a_l> (Eq. rho1) through the single-jump map.
+ * Deterministic fixed-order reduction in ws_d (mc_workspace_size(RHO1)). */
+int mc_rho1(int32_t N, int32_t M, const mc_tables *t, const double *C_d,
+            double *rho1_d, void *ws_d, size_t ws_bytes, mc_stream stream);
+
+/* rho2_d [M^4] = <a+_k a+_s a_q a_l> (Eq. rho2) through the double-jump map,
+ * deterministic fixed-order reduction in ws_d (mc_workspace_size(RHO2)). */
+int mc_rho2(int32_t N, int32_t M, const mc_tables *t, const double *C_d,
+            double *rho2_d, void *ws_d, size_t ws_bytes, mc_stream stream);
+
+/* out_d[1] complex = sum_i conj(x_i) y_i over n elements, fixed-order
+ * reduction in ws_d (mc_workspace_size(DOT) for n = D of (N, M), or any
+ * ws of at least 16 * MC_DOT_BLOCKS + 16 bytes). */
+#define MC_DOT_BLOCKS 1024
+int mc_zdotc(int64_t n, const double *x_d, const double *y_d, double *out_d,
+             void *ws_d, size_t ws_bytes, mc_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MC_H */

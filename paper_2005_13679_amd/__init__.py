@@ -1,0 +1,32 @@
+"""MI355X-native bosonic multiconfigurational operators (arXiv:2005.13679).
+
+Fock-space hashing, single/double jump maps, the many-body Hamiltonian apply
+H.C and the reduced density matrices, as hand-written HIP kernels for gfx950
+behind the C ABI of ``include/mc.h``.  This package is the thin Python
+binding: torch provides device memory and streams, the library does all the
+arithmetic.  There is no CPU fallback.
+"""
+
+from ._lib import MCError, LIB_PATH
+from .api import (
+    Tables,
+    apply_H,
+    build_tables,
+    dim,
+    hash_batch,
+    hash_occ,
+    rho1,
+    rho2,
+    t2_lookup,
+    tables_size,
+    unhash,
+    unhash_batch,
+    workspace_size,
+    zdotc,
+)
+
+__all__ = [
+    "MCError", "LIB_PATH", "Tables", "apply_H", "build_tables", "dim", "hash_batch",
+    "hash_occ", "rho1", "rho2", "t2_lookup", "tables_size", "unhash", "unhash_batch",
+    "workspace_size", "zdotc",
+]

@@ -1,0 +1,122 @@
+"""ctypes declarations for libmc.so (the C ABI in include/mc.h).
+
+The library is loaded from this package directory.  There is no fallback: if
+libmc.so is missing or fails to load, every call raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmc.so")
+
+MC_OK = 0
+MC_EINVAL = -1
+MC_ERANGE = -2
+MC_ENOMEM = -3
+MC_EHIP = -4
+
+MC_OP_APPLY = 1
+MC_OP_RHO1 = 2
+MC_OP_RHO2 = 3
+MC_OP_DOT = 4
+
+MC_MAX_M = 32
+MC_MAX_N = 65535
+MC_TILE = 64
+MC_DOT_BLOCKS = 1024
+
+c_i32, c_i64, c_p, c_sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t
+
+
+class TableSizes(ctypes.Structure):
+    _fields_ = [
+        ("dim", c_i64),
+        ("tiles", c_i64),
+        ("occ_bytes", c_i32),
+        ("pair_words", c_i32),
+        ("binom_bytes", c_i64),
+        ("occ_bytes_total", c_i64),
+        ("t1_bytes", c_i64),
+        ("pmask_bytes", c_i64),
+        ("t2_off_bytes", c_i64),
+        ("t2_compact_entries", c_i64),
+    ]
+
+
+class CTables(ctypes.Structure):
+    _fields_ = [
+        ("N", c_i32),
+        ("M", c_i32),
+        ("dim", c_i64),
+        ("tiles", c_i64),
+        ("binom_d", c_p),
+        ("occ_d", c_p),
+        ("t1_d", c_p),
+        ("pmask_d", c_p),
+        ("t2_off_d", c_p),
+        ("t2_d", c_p),
+        ("t2_entries", c_i64),
+        ("t2_required", c_i64),
+    ]
+
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "mc_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "mc_last_hip_error": (ctypes.c_int, []),
+    "mc_dim": (c_i64, [c_i32, c_i32]),
+    "mc_hash": (ctypes.c_int, [c_i32, c_i32, c_p, c_p]),
+    "mc_unhash": (ctypes.c_int, [c_i32, c_i32, c_i64, c_p]),
+    "mc_tables_size": (ctypes.c_int, [c_i32, c_i32, ctypes.POINTER(TableSizes)]),
+    "mc_build_jump_tables": (ctypes.c_int, [c_i32, c_i32, ctypes.POINTER(CTables), c_p]),
+    "mc_build_double_jumps": (ctypes.c_int, [c_i32, c_i32, ctypes.POINTER(CTables), c_p]),
+    "mc_hash_batch": (ctypes.c_int, [c_i32, c_i32, ctypes.POINTER(CTables), c_p, c_p, c_i64, c_p]),
+    "mc_unhash_batch": (ctypes.c_int, [c_i32, c_i32, ctypes.POINTER(CTables), c_p, c_p, c_i64, c_p]),
+    "mc_t2_lookup": (ctypes.c_int, [c_i32, c_i32, ctypes.POINTER(CTables), c_p, c_p, c_i64, c_p]),
+    "mc_workspace_size": (ctypes.c_int, [c_i32, c_i32, c_i32, ctypes.POINTER(c_sz)]),
+    "mc_apply_H": (ctypes.c_int, [c_i32, c_i32, c_p, c_p, ctypes.POINTER(CTables), c_p, c_p,
+                                  c_p, c_sz, c_p]),
+    "mc_rho1": (ctypes.c_int, [c_i32, c_i32, ctypes.POINTER(CTables), c_p, c_p, c_p, c_sz, c_p]),
+    "mc_rho2": (ctypes.c_int, [c_i32, c_i32, ctypes.POINTER(CTables), c_p, c_p, c_p, c_sz, c_p]),
+    "mc_zdotc": (ctypes.c_int, [c_i64, c_p, c_p, c_p, c_p, c_sz, c_p]),
+}
+
+
+class MCError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        lib = _lib
+        text = lib.mc_strerror(status).decode() if lib is not None else "?"
+        hip = lib.mc_last_hip_error() if lib is not None else 0
+        super().__init__(f"{where}: {text} (status {status}, last HIP error {hip})")
+        self.status = status
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+def load():
+    """Loads libmc.so once and declares every exported symbol."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is not built; run `python -m paper_2005_13679_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+        return lib
+
+
+def check(status: int, where: str) -> None:
+    if status != MC_OK:
+        raise MCError(status, where)

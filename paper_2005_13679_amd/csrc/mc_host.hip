@@ -1,0 +1,159 @@
+// Host-side part of the C ABI: status codes, combinatorics, size queries and
+// argument validation.  No device work happens here.
+#include <string.h>
+
+#include "mc_internal.h"
+
+namespace mc {
+
+static thread_local int g_last_hip_error = 0;
+
+int set_hip_error(hipError_t e)
+{
+    if (e == hipSuccess) return MC_OK;
+    g_last_hip_error = (int)e;
+    return MC_EHIP;
+}
+
+int launch_status() { return set_hip_error(hipGetLastError()); }
+
+int check_nm(int32_t N, int32_t M)
+{
+    if (M < 1 || M > MC_MAX_M) return MC_EINVAL;
+    if (N < 1 || N > MC_MAX_N) return MC_EINVAL;
+    return MC_OK;
+}
+
+// C(a, b) with 128-bit intermediates; -1 if the result exceeds int64.
+static int64_t binom_checked(int64_t a, int64_t b)
+{
+    if (b < 0 || a < 0 || b > a) return 0;
+    if (b > a - b) b = a - b;
+    unsigned __int128 r = 1;
+    for (int64_t i = 1; i <= b; ++i) {
+        r = r * (unsigned __int128)(a - b + i) / (unsigned __int128)i;
+        if (r > (unsigned __int128)INT64_MAX) return -1;
+    }
+    return (int64_t)r;
+}
+
+int64_t dim_checked(int32_t N, int32_t M) { return binom_checked((int64_t)N + M - 1, N); }
+
+bool overlaps(const void *a, size_t na, const void *b, size_t nb)
+{
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + nb && y < x + na;
+}
+
+int check_tables(int32_t N, int32_t M, const mc_tables *t, bool need_t2)
+{
+    if (!t) return MC_EINVAL;
+    if (t->N != N || t->M != M) return MC_EINVAL;
+    const int64_t D = dim_checked(N, M);
+    if (D <= 0 || t->dim != D) return MC_EINVAL;
+    if (t->tiles != (D + kTile - 1) / kTile) return MC_EINVAL;
+    if (!t->binom_d || !t->occ_d || !t->t1_d || !t->pmask_d || !t->t2_off_d) return MC_EINVAL;
+    if (need_t2) {
+        if (!t->t2_d || t->t2_required < 0) return MC_EINVAL;
+        if (t->t2_entries < t->t2_required) return MC_ENOMEM;
+    }
+    return MC_OK;
+}
+
+}  // namespace mc
+
+using namespace mc;
+
+extern "C" {
+
+const char *mc_strerror(int status)
+{
+    switch (status) {
+    case MC_OK: return "success";
+    case MC_EINVAL: return "invalid argument";
+    case MC_ERANGE: return "value out of range";
+    case MC_ENOMEM: return "buffer or workspace too small";
+    case MC_EHIP: return "HIP runtime error";
+    default: return "unknown status";
+    }
+}
+
+int mc_last_hip_error(void) { return g_last_hip_error; }
+
+int64_t mc_dim(int32_t N, int32_t M)
+{
+    if (N < 0 || M < 1) return MC_EINVAL;
+    const int64_t D = dim_checked(N, M);
+    return D < 0 ? (int64_t)MC_ERANGE : D;
+}
+
+int mc_hash(int32_t N, int32_t M, const int32_t *occ, int64_t *index)
+{
+    if (!occ || !index || N < 0 || M < 1 || M > MC_MAX_M) return MC_EINVAL;
+    int64_t sum = 0;
+    for (int m = 0; m < M; ++m) {
+        if (occ[m] < 0) return MC_EINVAL;
+        sum += occ[m];
+    }
+    if (sum != N) return MC_EINVAL;
+    if (dim_checked(N, M) < 0) return MC_ERANGE;
+    int64_t idx = 0;
+    int64_t S = occ[0];
+    for (int m = 1; m < M; ++m) {
+        const int64_t Sp = S;
+        S += occ[m];
+        idx += binom_checked(S + m, m) - binom_checked(Sp + m, m);
+    }
+    *index = idx;
+    return MC_OK;
+}
+
+int mc_unhash(int32_t N, int32_t M, int64_t index, int32_t *occ)
+{
+    if (!occ || N < 0 || M < 1 || M > MC_MAX_M) return MC_EINVAL;
+    const int64_t D = dim_checked(N, M);
+    if (D < 0) return MC_ERANGE;
+    if (index < 0 || index >= D) return MC_ERANGE;
+    int64_t r = index;
+    int64_t S = N;
+    for (int m = M - 1; m >= 1; --m) {
+        const int64_t top = binom_checked(S + m, m);
+        const int64_t need = top - r;
+        int64_t lo = 0, hi = S;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (binom_checked(mid + m, m) >= need) hi = mid;
+            else lo = mid + 1;
+        }
+        occ[m] = (int32_t)(S - lo);
+        r -= top - binom_checked(lo + m, m);
+        S = lo;
+    }
+    occ[0] = (int32_t)S;
+    return MC_OK;
+}
+
+int mc_tables_size(int32_t N, int32_t M, mc_table_sizes *out)
+{
+    if (!out) return MC_EINVAL;
+    int st = check_nm(N, M);
+    if (st) return st;
+    const int64_t D = dim_checked(N, M);
+    if (D < 0 || D >= ((int64_t)1 << 31)) return MC_ERANGE;
+    memset(out, 0, sizeof(*out));
+    const int64_t tiles = (D + kTile - 1) / kTile;
+    out->dim = D;
+    out->tiles = tiles;
+    out->occ_bytes = occ_width(N);
+    out->pair_words = pair_words(M);
+    out->binom_bytes = (int64_t)(N + 3) * (M + 1) * 8;
+    out->occ_bytes_total = tiles * M * kTile * out->occ_bytes;
+    out->t1_bytes = tiles * M * M * kTile * 4;
+    out->pmask_bytes = tiles * out->pair_words * 8;
+    out->t2_off_bytes = (tiles + 1) * 8;
+    const int64_t pairs_total = N >= 2 ? dim_checked(N - 2, M) : 0;
+    out->t2_compact_entries = (int64_t)M * M * npairs(M) * pairs_total;
+    return MC_OK;
+}
+
+}  // extern "C"

@@ -26,3 +26,31 @@ def oracle_native():
     from oracle import native
     native.build(force=False)
     return native
+
+
+@pytest.fixture(autouse=True)
+def _announce_gpu_case(request):
+    """Name each GPU case on stdout (flushed) before it touches the device."""
+    if request.node.get_closest_marker("gpu") is not None:
+        print(f"\n[gpu-case] {request.node.nodeid}", flush=True)
+    yield
+
+
+def gpu_available():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+@pytest.fixture(scope="session")
+def mc():
+    """The HIP library binding; fails (not skips) if the library is missing."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2005_13679_amd as mcl
+    from paper_2005_13679_amd import _lib
+    _lib.load()
+    return mcl

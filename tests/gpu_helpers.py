@@ -1,0 +1,71 @@
+"""Helpers for GPU parity tests: host-side remapping of the tiled tables and
+the relative infinity-norm used as the floating-point bar."""
+
+import numpy as np
+
+TILE = 64
+
+
+def rel_inf(a, b) -> float:
+    a = np.asarray(a)
+    b = np.asarray(b)
+    den = np.max(np.abs(b)) if b.size else 0.0
+    if den == 0.0:
+        return float(np.max(np.abs(a - b))) if a.size else 0.0
+    return float(np.max(np.abs(a - b)) / den)
+
+
+def pair_list(M):
+    return [(k, s) for k in range(M) for s in range(k, M)]
+
+
+def pair_valid(occ, k, s):
+    """occ: (R, M) array -> bool (R,)"""
+    if k == s:
+        return occ[:, k] >= 2
+    return (occ[:, k] >= 1) & (occ[:, s] >= 1)
+
+
+def tiled_t2_check_and_rows(tables, rows):
+    """Reads the tiled double-jump map back and returns, for each requested
+    row, its entries in the paper's per-row layout (valid removal pairs in
+    lexicographic order, M*M slots each).  Also asserts the layout invariants:
+    pair mask = union of valid pairs over the tile, offsets consistent with
+    the mask, and -1 padding for rows that cannot lose a pair."""
+    M, D = tables.M, tables.dim
+    P = M * (M + 1) // 2
+    W = (P + 63) // 64
+    occ = tables.occupations()
+    t2 = tables.t2.cpu().numpy()
+    off = tables.t2_off.cpu().numpy()
+    pm_words = tables.pmask.cpu().numpy().view(np.uint64).reshape(tables.tiles, W)
+    bits = np.zeros((tables.tiles, P), dtype=bool)
+    for p in range(P):
+        bits[:, p] = (pm_words[:, p // 64] >> np.uint64(p % 64)) & np.uint64(1) == 1
+    # mask is exactly the union over the tile's rows
+    occ_pad = np.zeros((tables.tiles * TILE, M), dtype=np.int64)
+    occ_pad[:D] = occ
+    for p, (k, s) in enumerate(pair_list(M)):
+        v = pair_valid(occ_pad, k, s).reshape(tables.tiles, TILE).any(axis=1)
+        assert np.array_equal(v, bits[:, p]), ("pair mask", p)
+    counts = bits.sum(axis=1).astype(np.int64) * M * M * TILE
+    assert off[0] == 0 and np.array_equal(np.diff(off), counts), "t2 offsets"
+    assert tables.t2_required == off[-1]
+    rank = np.cumsum(bits, axis=1) - 1
+    out = []
+    for g in np.asarray(rows, dtype=np.int64):
+        tile, lane = divmod(int(g), TILE)
+        ent = []
+        for p, (k, s) in enumerate(pair_list(M)):
+            if not bits[tile, p]:
+                continue
+            base = off[tile] + rank[tile, p] * M * M * TILE + lane
+            blk = t2[base + np.arange(M * M) * TILE]
+            n = occ[g]
+            ok = (n[k] >= 2) if k == s else (n[k] >= 1 and n[s] >= 1)
+            if ok:
+                ent.append(blk)
+            else:
+                assert np.all(blk == -1), ("padding", g, p)
+        out.append(np.concatenate(ent) if ent else np.zeros(0, np.int32))
+    return out

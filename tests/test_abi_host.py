@@ -1,0 +1,152 @@
+"""The C-ABI library loads, exports what include/mc.h declares, and its
+host-side logic (dimension, hash, unhash, sizes, error paths) agrees with the
+oracle.  No device work: these run without a GPU."""
+
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import combinatorics as cb
+from tests.conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "mc.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mc_[A-Za-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2005_13679_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libmc.so is not built (run python -m paper_2005_13679_amd.build)")
+    return _lib.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    from paper_2005_13679_amd import _lib
+    assert set(names) == set(_lib.SIGNATURES), "binding and header disagree"
+
+
+def test_struct_layouts_match_header():
+    from paper_2005_13679_amd import _lib
+    assert ctypes.sizeof(_lib.CTables) == 8 + 8 * 2 + 8 * 6 + 8 * 2
+    assert ctypes.sizeof(_lib.TableSizes) == 8 * 2 + 4 * 2 + 8 * 6
+
+
+def test_strerror(lib):
+    for code in (0, -1, -2, -3, -4, 17):
+        assert isinstance(lib.mc_strerror(code), bytes)
+
+
+@pytest.mark.parametrize("N,M", [(10, 5), (20, 7), (200, 5), (50, 6), (1, 1), (5, 25), (1000, 3)])
+def test_dim(lib, N, M):
+    assert lib.mc_dim(N, M) == cb.dim(N, M)
+
+
+def test_dim_errors(lib):
+    assert lib.mc_dim(-1, 3) == -1
+    assert lib.mc_dim(3, 0) == -1
+    assert lib.mc_dim(10000, 30) == -2      # does not fit in int64
+
+
+@pytest.mark.parametrize("N,M", [(3, 5), (10, 5), (7, 4), (1, 6), (4, 1), (12, 3)])
+def test_hash_unhash_full_enumeration(N, M):
+    import paper_2005_13679_amd as mc
+    for c in cb.compositions(N, M):
+        i = mc.hash_occ(N, M, c)
+        assert i == cb.hash_alg1(c)
+        assert list(mc.unhash(N, M, i)) == c
+
+
+def test_worked_example():
+    import paper_2005_13679_amd as mc
+    assert mc.hash_occ(3, 5, [0, 1, 0, 2, 0]) == 17
+    assert list(mc.unhash(3, 5, 17)) == [0, 1, 0, 2, 0]
+
+
+def test_large_space_samples(oracle_native):
+    import paper_2005_13679_amd as mc
+    N, M = 200, 5
+    rng = np.random.default_rng(3)
+    D = cb.dim(N, M)
+    rows = rng.integers(0, D, 500)
+    occ = oracle_native.occ_rows(N, M, rows)
+    for r, o in zip(rows, occ):
+        assert list(mc.unhash(N, M, int(r))) == list(o)
+        assert mc.hash_occ(N, M, o) == r
+
+
+def test_hash_unhash_errors(lib):
+    import paper_2005_13679_amd as mc
+    occ = (ctypes.c_int32 * 3)(1, 1, 1)
+    idx = ctypes.c_int64()
+    assert lib.mc_hash(4, 3, occ, ctypes.byref(idx)) == -1          # sum != N
+    neg = (ctypes.c_int32 * 3)(2, -1, 2)
+    assert lib.mc_hash(3, 3, neg, ctypes.byref(idx)) == -1          # negative occupation
+    assert lib.mc_hash(3, 3, None, ctypes.byref(idx)) == -1
+    out = (ctypes.c_int32 * 3)()
+    assert lib.mc_unhash(3, 3, 10, out) == -2                       # D = 10
+    assert lib.mc_unhash(3, 3, -1, out) == -2
+    assert lib.mc_unhash(3, 3, 9, out) == 0 and list(out) == [0, 0, 3]
+    with pytest.raises(mc.MCError):
+        mc.unhash(3, 3, 10)
+
+
+def test_tables_size(lib):
+    import paper_2005_13679_amd as mc
+    for N, M in [(10, 5), (200, 5), (50, 6), (20, 7), (300, 2), (2, 9)]:
+        s = mc.tables_size(N, M)
+        D = cb.dim(N, M)
+        tiles = (D + 63) // 64
+        assert s.dim == D and s.tiles == tiles
+        assert s.occ_bytes == (1 if N <= 255 else 2)
+        assert s.t1_bytes == tiles * M * M * 64 * 4
+        assert s.t2_off_bytes == (tiles + 1) * 8
+        assert s.pair_words == (M * (M + 1) // 2 + 63) // 64
+        assert s.t2_compact_entries == M * M * (M * (M + 1) // 2) * cb.nc(N - 2, M)
+    # the large workload: 2.525e10 compact double-jump entries (101 GB int32)
+    s = mc.tables_size(200, 5)
+    assert s.t2_compact_entries == 25 * 15 * cb.nc(198, 5)
+    sz = mc.tables_size.__wrapped__ if hasattr(mc.tables_size, "__wrapped__") else None
+    st = mc._lib.TableSizes()
+    assert lib.mc_tables_size(40, 30, ctypes.byref(st)) == -2         # D >= 2^31
+    assert lib.mc_tables_size(0, 3, ctypes.byref(st)) == -1
+    assert lib.mc_tables_size(3, 33, ctypes.byref(st)) == -1
+    assert lib.mc_tables_size(3, 3, None) == -1
+
+
+def test_workspace_size(lib):
+    import paper_2005_13679_amd as mc
+    assert mc.workspace_size(10, 5, 1) == 15 * 25 * 16
+    assert mc.workspace_size(10, 5, 2) > 0 and mc.workspace_size(10, 5, 3) > 0
+    b = ctypes.c_size_t()
+    assert lib.mc_workspace_size(10, 5, 99, ctypes.byref(b)) == -1
+
+
+def test_device_entry_points_reject_bad_arguments_before_launch(lib):
+    """Argument checks run on the host before anything is enqueued."""
+    from paper_2005_13679_amd import _lib as L
+    t = L.CTables()
+    t.N, t.M, t.dim, t.tiles = 10, 5, 1001, 16
+    # missing buffers
+    assert lib.mc_build_jump_tables(10, 5, ctypes.byref(t), None) == -1
+    assert lib.mc_apply_H(10, 5, None, None, ctypes.byref(t), None, None, None, 0, None) == -1
+    # mismatched N
+    assert lib.mc_build_jump_tables(11, 5, ctypes.byref(t), None) == -1
+    assert lib.mc_rho1(10, 5, None, None, None, None, 0, None) == -1
+    assert lib.mc_zdotc(-1, None, None, None, None, 0, None) == -1
+    # wrong tile count
+    t.tiles = 15
+    assert lib.mc_build_jump_tables(10, 5, ctypes.byref(t), None) == -1
