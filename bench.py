@@ -107,6 +107,8 @@ def main(argv=None):
     ap.add_argument("--workload", default="large_random", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--extras", action="store_true", help="also time rho1/rho2 passes")
+    ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
+                    help="run one elementwise copy of this size first (HBM counter scale)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -134,6 +136,15 @@ def main(argv=None):
     hd = torch.from_numpy(h).to(dev)
     gd = torch.from_numpy(g).to(dev)
     HC = torch.empty_like(Cd)
+
+    if args.copy_calibration_gib > 0:
+        n = int(args.copy_calibration_gib * (1 << 30)) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 1.0, out=dst)   # reads and writes n * 8 bytes
+        torch.cuda.synchronize()
+        del src, dst
 
     for _ in range(args.warmup):
         mc.apply_H(hd, gd, Cd, tab, out=HC)

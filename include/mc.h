@@ -184,12 +184,24 @@ int mc_workspace_size(int32_t N, int32_t M, int32_t op, size_t *bytes);
  * with G'_{ks,ql} = g_ksql + g_skql (k < s), g_kkql (k = s),
  * A_ks = sqrt(n_k n_s) or sqrt(n_k(n_k-1)), and B_ql the creation amplitudes
  * on m = n - e_k - e_s (sqrt((m_q+1)(m_l+1)), or sqrt((m_q+1)(m_q+2)) if
- * q = l).  h_d [M*M], g_d [M^4], C_d and HC_d [D] complex128 on the device;
- * HC_d must not overlap C_d (MC_EINVAL).  ws_d: mc_workspace_size(APPLY).
+ * q = l).  If the tables were built without the double-jump map
+ * (t->t2_d == NULL), each double-jump target is found as two chained single
+ * jumps, T1[T1[g][k][q]][s][l] (M <= 8), and no double-jump table is read.
+ * h_d [M*M], g_d [M^4], C_d and HC_d [D] complex128 on the device;
+ * HC_d must not overlap C_d (MC_EINVAL).  ws_d: mc_workspace_size(APPLY);
+ * the call stages h and G' there, so concurrent calls need separate ws.
  * No symmetry of h or g is assumed. */
 int mc_apply_H(int32_t N, int32_t M, const double *h_d, const double *g_d,
                const mc_tables *t, const double *C_d, double *HC_d,
                void *ws_d, size_t ws_bytes, mc_stream stream);
+
+/* HC_d = H^dagger . C_d, the same apply with h -> h^dagger
+ * (conj(h_lk)) and g -> g^dagger (g^dagger_ksql = conj(g_lqsk)).  Equals
+ * mc_apply_H when H is Hermitian; needed for gradients of E = <C|H C> with
+ * non-Hermitian inputs.  Same arguments and errors as mc_apply_H. */
+int mc_apply_H_adjoint(int32_t N, int32_t M, const double *h_d, const double *g_d,
+                       const mc_tables *t, const double *C_d, double *HC_d,
+                       void *ws_d, size_t ws_bytes, mc_stream stream);
 
 /* rho1_d [M*M] = <a+_k a_l> (Eq. rho1) through the single-jump map.
  * Deterministic fixed-order reduction in ws_d (mc_workspace_size(RHO1)). */
@@ -207,6 +219,50 @@ int mc_rho2(int32_t N, int32_t M, const mc_tables *t, const double *C_d,
 #define MC_DOT_BLOCKS 1024
 int mc_zdotc(int64_t n, const double *x_d, const double *y_d, double *out_d,
              void *ws_d, size_t ws_bytes, mc_stream stream);
+
+/* out_d[i] = scale * (op(a) op(x_i) + op(b) op(y_i)) for i < n, complex128,
+ * with device scalars a_d, b_d (NULL = 1) and op = complex conjugation where
+ * the matching MC_CONJ_* bit of `flags` is set; y_d = NULL drops the second
+ * term.  out_d may alias x_d or y_d element-wise.  Used for the gradient
+ * combinations of the energy functional (no host arithmetic in the path). */
+#define MC_CONJ_A 1u
+#define MC_CONJ_X 2u
+#define MC_CONJ_B 4u
+#define MC_CONJ_Y 8u
+int mc_zaxpby(int64_t n, const double *a_d, const double *x_d, const double *b_d,
+              const double *y_d, double scale, uint32_t flags, double *out_d, mc_stream stream);
+
+/* ------------------------------------------------------------------------ */
+/* Lanczos building blocks (Sec. VI: Lanczos tridiagonalisation with full   */
+/* reorthogonalisation).  Scalars stay on the device.                        */
+/* ------------------------------------------------------------------------ */
+
+/* c_d[k] = sum_i conj(V_d[k*ldv + i]) w_d[i] for k < K (complex128), each a
+ * fixed-order reduction.  ws_d: K * 64 * 16 bytes. */
+int mc_zgemv_c(int32_t K, int64_t n, const double *V_d, int64_t ldv, const double *w_d,
+               double *c_d, void *ws_d, size_t ws_bytes, mc_stream stream);
+
+/* w_d[i] -= sum_{k<K} V_d[k*ldv + i] c_d[k] (complex128), k in order. */
+int mc_zgemv_sub(int32_t K, int64_t n, const double *V_d, int64_t ldv, const double *c_d,
+                 double *w_d, mc_stream stream);
+
+/* beta = ||w_d|| (fixed-order reduction), out_d = w_d / beta (0 if beta = 0);
+ * beta is written to beta_d[0] (double, may be NULL).  out_d may equal w_d.
+ * ws_d: (MC_DOT_BLOCKS + 2) * 16 bytes. */
+int mc_normalize(int64_t n, const double *w_d, double *out_d, double *beta_d, void *ws_d,
+                 size_t ws_bytes, mc_stream stream);
+
+/* Three-term Lanczos step without reorthogonalisation:
+ * w_d -= Re(alpha_d[0]) v_d + beta_prev_d[0] vprev_d  (complex128 vectors,
+ * alpha complex128 and beta double on the device; vprev_d or beta_prev_d
+ * NULL drops the second term). */
+int mc_lanczos_orth(int64_t n, double *w_d, const double *v_d, const double *vprev_d,
+                    const double *alpha_d, const double *beta_prev_d, mc_stream stream);
+
+/* Lowest eigenvalue of the real symmetric tridiagonal matrix with diagonal
+ * alpha[K] and off-diagonal beta[K-1] (host arrays), by Sturm-sequence
+ * bisection.  Host only. */
+int mc_tridiag_lowest(int32_t K, const double *alpha, const double *beta, double *e0);
 
 #ifdef __cplusplus
 }

@@ -11,6 +11,7 @@ from ._lib import MCError, LIB_PATH
 from .api import (
     Tables,
     apply_H,
+    apply_H_adjoint,
     build_tables,
     dim,
     hash_batch,
@@ -22,11 +23,13 @@ from .api import (
     unhash,
     unhash_batch,
     workspace_size,
+    zaxpby,
     zdotc,
 )
+from .autograd import Energy, energy
 
 __all__ = [
-    "MCError", "LIB_PATH", "Tables", "apply_H", "build_tables", "dim", "hash_batch",
+    "MCError", "LIB_PATH", "Energy", "Tables", "apply_H", "apply_H_adjoint", "energy", "build_tables", "dim", "hash_batch",
     "hash_occ", "rho1", "rho2", "t2_lookup", "tables_size", "unhash", "unhash_batch",
-    "workspace_size", "zdotc",
+    "workspace_size", "zaxpby", "zdotc",
 ]

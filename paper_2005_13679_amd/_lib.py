@@ -29,6 +29,11 @@ MC_MAX_N = 65535
 MC_TILE = 64
 MC_DOT_BLOCKS = 1024
 
+MC_CONJ_A = 1
+MC_CONJ_X = 2
+MC_CONJ_B = 4
+MC_CONJ_Y = 8
+
 c_i32, c_i64, c_p, c_sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t
 
 
@@ -80,9 +85,18 @@ SIGNATURES = {
     "mc_workspace_size": (ctypes.c_int, [c_i32, c_i32, c_i32, ctypes.POINTER(c_sz)]),
     "mc_apply_H": (ctypes.c_int, [c_i32, c_i32, c_p, c_p, ctypes.POINTER(CTables), c_p, c_p,
                                   c_p, c_sz, c_p]),
+    "mc_apply_H_adjoint": (ctypes.c_int, [c_i32, c_i32, c_p, c_p, ctypes.POINTER(CTables), c_p,
+                                          c_p, c_p, c_sz, c_p]),
+    "mc_zaxpby": (ctypes.c_int, [c_i64, c_p, c_p, c_p, c_p, ctypes.c_double, ctypes.c_uint32,
+                                 c_p, c_p]),
     "mc_rho1": (ctypes.c_int, [c_i32, c_i32, ctypes.POINTER(CTables), c_p, c_p, c_p, c_sz, c_p]),
     "mc_rho2": (ctypes.c_int, [c_i32, c_i32, ctypes.POINTER(CTables), c_p, c_p, c_p, c_sz, c_p]),
     "mc_zdotc": (ctypes.c_int, [c_i64, c_p, c_p, c_p, c_p, c_sz, c_p]),
+    "mc_zgemv_c": (ctypes.c_int, [c_i32, c_i64, c_p, c_i64, c_p, c_p, c_p, c_sz, c_p]),
+    "mc_zgemv_sub": (ctypes.c_int, [c_i32, c_i64, c_p, c_i64, c_p, c_p, c_p]),
+    "mc_normalize": (ctypes.c_int, [c_i64, c_p, c_p, c_p, c_p, c_sz, c_p]),
+    "mc_tridiag_lowest": (ctypes.c_int, [c_i32, c_p, c_p, c_p]),
+    "mc_lanczos_orth": (ctypes.c_int, [c_i64, c_p, c_p, c_p, c_p, c_p, c_p]),
 }
 
 

@@ -205,6 +205,49 @@ def apply_H(h, g, C: torch.Tensor, tables: Tables, out: torch.Tensor | None = No
     return out
 
 
+def apply_H_adjoint(h, g, C: torch.Tensor, tables: Tables,
+                    out: torch.Tensor | None = None) -> torch.Tensor:
+    """H^dagger . C (h -> h^dagger, g_ksql -> conj(g_lqsk))."""
+    N, M, dev = tables.N, tables.M, tables.device
+    h = _as_dev(h, dev, (M, M))
+    g = _as_dev(g, dev, (M, M, M, M))
+    _require(C, "C", torch.complex128, dev, numel=tables.dim)
+    if out is None:
+        out = torch.empty_like(C)
+    _require(out, "out", torch.complex128, dev, numel=tables.dim)
+    ws = tables.workspace(L.MC_OP_APPLY)
+    with torch.cuda.device(dev):
+        L.check(L.load().mc_apply_H_adjoint(N, M, _ptr(h), _ptr(g), ctypes.byref(tables.c),
+                                            _ptr(C), _ptr(out), _ptr(ws), ws.numel(),
+                                            _stream(dev)), "mc_apply_H_adjoint")
+    return out
+
+
+def zaxpby(x: torch.Tensor, a: torch.Tensor | None = None, y: torch.Tensor | None = None,
+           b: torch.Tensor | None = None, scale: float = 1.0, conj_a=False, conj_x=False,
+           conj_b=False, conj_y=False, out: torch.Tensor | None = None) -> torch.Tensor:
+    """out = scale * (op(a) op(x) + op(b) op(y)) with 0-d device scalars a, b."""
+    dev = x.device
+    _require(x, "x", torch.complex128, dev)
+    if y is not None:
+        _require(y, "y", torch.complex128, dev, numel=x.numel())
+    for name, v in (("a", a), ("b", b)):
+        if v is not None:
+            _require(v, name, torch.complex128, dev, numel=1)
+    if out is None:
+        out = torch.empty_like(x)
+    _require(out, "out", torch.complex128, dev, numel=x.numel())
+    flags = ((L.MC_CONJ_A if conj_a else 0) | (L.MC_CONJ_X if conj_x else 0)
+             | (L.MC_CONJ_B if conj_b else 0) | (L.MC_CONJ_Y if conj_y else 0))
+    nul = ctypes.c_void_p(None)
+    with torch.cuda.device(dev):
+        L.check(L.load().mc_zaxpby(x.numel(), _ptr(a) if a is not None else nul, _ptr(x),
+                                   _ptr(b) if b is not None else nul,
+                                   _ptr(y) if y is not None else nul, float(scale), flags,
+                                   _ptr(out), _stream(dev)), "mc_zaxpby")
+    return out
+
+
 def rho1(C: torch.Tensor, tables: Tables, out: torch.Tensor | None = None) -> torch.Tensor:
     """One-body reduced density matrix rho_kl = <a+_k a_l> (Eq. rho1)."""
     M, dev = tables.M, tables.device

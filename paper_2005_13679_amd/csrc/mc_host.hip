@@ -1,5 +1,6 @@
 // Host-side part of the C ABI: status codes, combinatorics, size queries and
 // argument validation.  No device work happens here.
+#include <math.h>
 #include <string.h>
 
 #include "mc_internal.h"
@@ -153,6 +154,41 @@ int mc_tables_size(int32_t N, int32_t M, mc_table_sizes *out)
     out->t2_off_bytes = (tiles + 1) * 8;
     const int64_t pairs_total = N >= 2 ? dim_checked(N - 2, M) : 0;
     out->t2_compact_entries = (int64_t)M * M * npairs(M) * pairs_total;
+    return MC_OK;
+}
+
+// Lowest eigenvalue of the symmetric tridiagonal matrix with diagonal
+// alpha[K] and off-diagonal beta[K-1], by bisection on the Sturm count (the
+// number of negative pivots of T - x I in its LDL^T factorisation equals the
+// number of eigenvalues below x).
+int mc_tridiag_lowest(int32_t K, const double *alpha, const double *beta, double *e0)
+{
+    if (K < 1 || !alpha || !e0 || (K > 1 && !beta)) return MC_EINVAL;
+    double lo = alpha[0], hi = alpha[0];
+    for (int i = 0; i < K; ++i) {
+        const double r = (i > 0 ? fabs(beta[i - 1]) : 0.0) + (i < K - 1 ? fabs(beta[i]) : 0.0);
+        lo = fmin(lo, alpha[i] - r);
+        hi = fmax(hi, alpha[i] + r);
+    }
+    const double tiny = 1e-300;
+    auto below = [&](double x) {
+        int cnt = 0;
+        double d = alpha[0] - x;
+        if (d < 0) ++cnt;
+        for (int i = 1; i < K; ++i) {
+            if (fabs(d) < tiny) d = d < 0 ? -tiny : tiny;
+            d = alpha[i] - x - beta[i - 1] * beta[i - 1] / d;
+            if (d < 0) ++cnt;
+        }
+        return cnt;
+    };
+    for (int it = 0; it < 200 && hi - lo > 0; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (below(mid) >= 1) hi = mid;
+        else lo = mid;
+    }
+    *e0 = 0.5 * (lo + hi);
     return MC_OK;
 }
 

@@ -145,6 +145,15 @@ __device__ __forceinline__ void t2_block(const int64_t *__restrict__ t2_off, int
     off0 = off0 > 0 ? off0 : 0;
 }
 
+// Index of the calling wavefront within its block, as a wave-uniform (SGPR)
+// value: the compiler cannot prove threadIdx.x >> 6 uniform by itself, and
+// anything derived from a divergent value (tile, offsets, buffer resources)
+// would force per-lane waterfall loops around every buffer load.
+__device__ __forceinline__ int wave_in_block()
+{
+    return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+}
+
 // Maps a hardware block index to a logical one so that each of the 8 XCDs
 // (which receive blocks round-robin) works on a contiguous range of blocks;
 // neighbouring tiles then share the XCD's L2.

@@ -9,20 +9,39 @@
 // from an empty orbital) and padding rows load through a range-checked
 // buffer resource and read as zero, so the inner loops have no branches on
 // row validity; only the tile-uniform pair mask branches.
+#include <utility>
+
 #include "mc_internal.h"
 
 namespace mc {
 
-// G'_{p,ql} = (g_ksql + g_skql)/2 for k < s, g_kkql/2 for k = s, where p is
-// the index of the removal pair (k, s), k <= s, in lexicographic order.  The
-// two ordered removals (k, s) and (s, k) reach the same configuration, so
-// their coefficients add; the 1/2 is the interaction prefactor.
-__global__ void k_gprime(int M, const double2 *__restrict__ g, double2 *__restrict__ gp)
+// Per-call coefficient staging into the workspace:
+//   hp[k*M + l]   = h_kl                      (or conj(h_lk) for H^dagger)
+//   gp[p*M*M + ql] = G'_{p,ql} = (g_ksql + g_skql)/2 for k < s, g_kkql/2 for
+//                    k = s, where p is the index of the removal pair (k, s),
+//                    k <= s, in lexicographic order.
+// The two ordered removals (k, s) and (s, k) reach the same configuration, so
+// their coefficients add; the 1/2 is the interaction prefactor.  For the
+// adjoint, g is replaced by g^dagger_ksql = conj(g_lqsk).
+__global__ void k_prep(int M, int adjoint, const double2 *__restrict__ g,
+                       const double2 *__restrict__ h, double2 *__restrict__ gp,
+                       double2 *__restrict__ hp)
 {
     const int P = M * (M + 1) / 2;
     const int total = P * M * M;
-    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+    auto gat = [&](int k, int s, int q, int l) -> double2 {
+        if (!adjoint) return g[((k * M + s) * M + q) * M + l];
+        const double2 v = g[((l * M + q) * M + s) * M + k];
+        return make_double2(v.x, -v.y);
+    };
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total + M * M;
          idx += gridDim.x * blockDim.x) {
+        if (idx >= total) {
+            const int e = idx - total, k = e / M, l = e % M;
+            const double2 v = adjoint ? h[l * M + k] : h[k * M + l];
+            hp[e] = make_double2(v.x, adjoint ? -v.y : v.y);
+            continue;
+        }
         const int p = idx / (M * M), ql = idx % (M * M);
         int k = 0, rem = p;
         while (rem >= M - k) {
@@ -31,9 +50,9 @@ __global__ void k_gprime(int M, const double2 *__restrict__ g, double2 *__restri
         }
         const int s = k + rem;
         const int q = ql / M, l = ql % M;
-        double2 a = g[((k * M + s) * M + q) * M + l];
+        double2 a = gat(k, s, q, l);
         if (k != s) {
-            const double2 b = g[((s * M + k) * M + q) * M + l];
+            const double2 b = gat(s, k, q, l);
             a.x += b.x;
             a.y += b.y;
         }
@@ -41,7 +60,6 @@ __global__ void k_gprime(int M, const double2 *__restrict__ g, double2 *__restri
     }
 }
 
-// Coefficient gather: C[t] for t in [0, D), zero for t = -1.
 // Vectors of up to 2^28 entries go through a range-checked buffer resource
 // (any t outside [0, D) reads zero); larger ones (BIGC) use 64-bit addresses
 // with an explicit range test.
@@ -88,76 +106,111 @@ __device__ __forceinline__ void load_row(const OccT *__restrict__ occ, int64_t t
     }
 }
 
-// Element k of a per-lane register array without run-time register indexing:
-// a chain of selects, folded to a plain access when k is a compile-time
-// constant after unrolling.
-template <int MA>
-__device__ __forceinline__ double pick(const double (&a)[MA], int k)
+// Removal pair p (lexicographic k <= s) -> (k, s), for compile-time use.
+__host__ __device__ constexpr int pair_k(int M, int p)
 {
-    double v = a[0];
-#pragma unroll
-    for (int m = 1; m < MA; ++m) v = (k == m) ? a[m] : v;
-    return v;
+    for (int k = 0; k < M; ++k) {
+        if (p < M - k) return k;
+        p -= M - k;
+    }
+    return -1;
+}
+__host__ __device__ constexpr int pair_s(int M, int p)
+{
+    for (int k = 0; k < M; ++k) {
+        if (p < M - k) return k + p;
+        p -= M - k;
+    }
+    return -1;
 }
 
-template <int MA>
-__device__ __forceinline__ int pick(const int (&a)[MA], int k)
-{
-    int v = a[0];
-#pragma unroll
-    for (int m = 1; m < MA; ++m) v = (k == m) ? a[m] : v;
-    return v;
-}
+// Slots of one removal pair handled per batch: a batch issues all its table
+// loads, then all its gathers, then the arithmetic.
+#ifndef MC_SLOT_BATCH
+#define MC_SLOT_BATCH 13
+#endif
+template <int MT>
+constexpr int kSlotBatch = MT * MT < MC_SLOT_BATCH ? MT * MT : MC_SLOT_BATCH;
 
-// Contribution of removal pair (k, s), k <= s, to one row:
-//   A_ks * sum_{q,l} G'_{p,ql} B_ql(m) C[T2 slot],   m = n - e_k - e_s.
-// Lanes whose row cannot lose (k, s) have A = 0 and table entries of -1.
-template <int MT, bool BIGC>
-__device__ __forceinline__ void pair_term(int M, int k, int s, int p, int rank, int lane,
-                                          const int (&n)[MT], const Roots<MT> &R,
-                                          __amdgpu_buffer_rsrc_t r2,
-                                          const double2 *__restrict__ gp,
+// Contribution of removal pair P = (K, S), K <= S, to one row:
+//   A_KS * sum_{q,l} G'_{P,ql} B_ql(m) C[T2 slot],   m = n - e_K - e_S,
+// with `blk` this tile's block of M*M*64 entries for the pair.  Lanes whose
+// row cannot lose (K, S) hold -1 entries (gathers read 0) and get A = 0.
+template <int MT, bool BIGC, int P>
+__device__ __forceinline__ void pair_term(const int32_t *blk, int lane, const int (&n)[MT],
+                                          const Roots<MT> &R, const double2 *__restrict__ gp,
                                           const Gather<BIGC> &ldc, double &ar, double &ai)
 {
-    const int nk = pick(n, k), ns = pick(n, s);
-    const bool valid = k == s ? nk >= 2 : (nk >= 1 && ns >= 1);
-    const double s0k = pick(R.s0, k);
-    const double A = valid ? s0k * (k == s ? pick(R.sm1, k) : pick(R.s0, s)) : 0.0;
+    constexpr int K = pair_k(MT, P), S = pair_s(MT, P);
+    constexpr int NS = MT * MT, SB = kSlotBatch<MT>;
+    const __amdgpu_buffer_rsrc_t r2 = make_rsrc(blk, (uint32_t)(NS * kTile * 4));
+    const bool valid = K == S ? n[K] >= 2 : (n[K] >= 1 && n[S] >= 1);
+    const double A = valid ? R.s0[K] * (K == S ? R.sm1[K] : R.s0[S]) : 0.0;
     // creation amplitudes on m: rq = sqrt(m_q + 1), dq = sqrt(m_q + 2)
     double rq[MT], dq[MT];
 #pragma unroll
     for (int q = 0; q < MT; ++q) {
-        const int d = (q == k) + (q == s);
+        const int d = (q == K) + (q == S);
         rq[q] = d == 0 ? R.sp1[q] : (d == 1 ? R.s0[q] : R.sm1[q]);
         dq[q] = d == 0 ? R.sp2[q] : (d == 1 ? R.sp1[q] : R.s0[q]);
     }
-    const double2 *G = gp + p * MT * MT;
-    const uint32_t sbase = (uint32_t)rank * (uint32_t)(MT * MT * kTile * 4);
+    const double2 *G = gp + P * NS;
     double br = 0.0, bi = 0.0;
 #pragma unroll
-    for (int q = 0; q < MT; ++q) {
+    for (int j0 = 0; j0 < NS; j0 += SB) {
+        int32_t t[SB];
+        double2 c[SB];
 #pragma unroll
-        for (int l = 0; l < MT; ++l) {
-            const int32_t t = buf_ld_i32(r2, lane * 4, sbase + (uint32_t)((q * MT + l) * kTile * 4));
+        for (int i = 0; i < SB; ++i)
+            if (j0 + i < NS) t[i] = buf_ld_i32(r2, (uint32_t)(((j0 + i) * kTile + lane) * 4), 0);
+#pragma unroll
+        for (int i = 0; i < SB; ++i)
+            if (j0 + i < NS) c[i] = ldc(t[i]);
+#pragma unroll
+        for (int i = 0; i < SB; ++i) {
+            const int j = j0 + i;
+            if (j >= NS) break;
+            const int q = j / MT, l = j % MT;
             const double B = q == l ? rq[q] * dq[q] : rq[q] * rq[l];
-            const double2 c = ldc(t);
-            const double cr = c.x * B, ci = c.y * B;
-            const double2 Gv = G[q * MT + l];
-            br += Gv.x * cr - Gv.y * ci;
-            bi += Gv.x * ci + Gv.y * cr;
+            const double cr = c[i].x * B, ci = c[i].y * B;
+            const double2 Gv = G[j];
+            br = fma(Gv.x, cr, br);
+            br = fma(-Gv.y, ci, br);
+            bi = fma(Gv.x, ci, bi);
+            bi = fma(Gv.y, cr, bi);
         }
     }
-    ar += A * br;
-    ai += A * bi;
+    ar = fma(A, br, ar);
+    ai = fma(A, bi, ai);
 }
 
-// H.C for a compile-time orbital count MT (1..8).  For MT <= 5 the loop over
-// removal pairs is fully unrolled; above that it stays rolled (the slot loops
-// are always unrolled) to keep the kernel body compact.
+// All removal pairs in order; each present pair is its own basic block
+// (uniform branch on the tile's pair mask), which keeps the scheduler from
+// hoisting later pairs' loads.
+template <int MT, bool BIGC, int... Ps>
+__device__ __forceinline__ void all_pairs(std::integer_sequence<int, Ps...>,
+                                          const uint64_t *pm, const int32_t *t2, int64_t off0,
+                                          int64_t off1, int lane, const int (&n)[MT],
+                                          const Roots<MT> &R, const double2 *__restrict__ gp,
+                                          const Gather<BIGC> &ldc, double &ar, double &ai)
+{
+    int64_t pos = off0;
+    (
+        [&] {
+            constexpr int NSB = MT * MT * kTile;
+            if (((pm[Ps >> 6] >> (Ps & 63)) & 1) && pos + NSB <= off1) {
+                pair_term<MT, BIGC, Ps>(t2 + pos, lane, n, R, gp, ldc, ar, ai);
+                pos += NSB;
+            }
+        }(),
+        ...);
+}
+
+// H.C for a compile-time orbital count MT (1..8); every orbital, pair and
+// slot index is a compile-time constant.
 template <int MT, typename OccT, bool BIGC>
 __global__ __launch_bounds__(256) void k_apply(int64_t D, int64_t tiles, int64_t nblocks,
-                                                int64_t cap,
-                                                const OccT *__restrict__ occ,
+                                                int64_t cap, const OccT *__restrict__ occ,
                                                 const int32_t *__restrict__ t1,
                                                 const uint64_t *__restrict__ pmask,
                                                 const int64_t *__restrict__ t2_off,
@@ -168,8 +221,10 @@ __global__ __launch_bounds__(256) void k_apply(int64_t D, int64_t tiles, int64_t
                                                 double2 *__restrict__ HC)
 {
     constexpr int M = MT;
+    constexpr int P = M * (M + 1) / 2;
+    constexpr int W = (P + 63) / 64;
     const int lane = threadIdx.x & 63;
-    const int64_t tile = xcd_block(blockIdx.x, nblocks) * 4 + (threadIdx.x >> 6);
+    const int64_t tile = xcd_block(blockIdx.x, nblocks) * 4 + wave_in_block();
     if (tile >= tiles) return;
     const int64_t g = tile * kTile + lane;
     const bool live = g < D;
@@ -187,8 +242,8 @@ __global__ __launch_bounds__(256) void k_apply(int64_t D, int64_t tiles, int64_t
 #pragma unroll
         for (int k = 0; k < M; ++k) {
             const double2 hk = h[k * M + k];
-            dr += hk.x * n[k];
-            di += hk.y * n[k];
+            dr = fma(hk.x, (double)n[k], dr);
+            di = fma(hk.y, (double)n[k], di);
         }
         ar = dr * cg.x - di * cg.y;
         ai = dr * cg.y + di * cg.x;
@@ -196,55 +251,212 @@ __global__ __launch_bounds__(256) void k_apply(int64_t D, int64_t tiles, int64_t
 
     // single jumps k -> l (k != l): h_kl sqrt(n_k (n_l + 1)) C[T1]
     {
+        constexpr int S1 = M * (M - 1);
         const __amdgpu_buffer_rsrc_t r1 =
             make_rsrc(t1 + tile * M * M * kTile, (uint32_t)(M * M * kTile * 4));
+        int32_t t[S1 > 0 ? S1 : 1];
+        int j = 0;
 #pragma unroll
-        for (int k = 0; k < M; ++k) {
+        for (int k = 0; k < M; ++k)
+#pragma unroll
+            for (int l = 0; l < M; ++l)
+                if (l != k) t[j++] = buf_ld_i32(r1, (uint32_t)(((k * M + l) * kTile + lane) * 4), 0);
+        double2 c[S1 > 0 ? S1 : 1];
+#pragma unroll
+        for (int i = 0; i < S1; ++i) c[i] = ldc(t[i]);
+        j = 0;
+#pragma unroll
+        for (int k = 0; k < M; ++k)
 #pragma unroll
             for (int l = 0; l < M; ++l) {
                 if (l == k) continue;
-                const int32_t t = buf_ld_i32(r1, lane * 4, (uint32_t)((k * M + l) * kTile * 4));
                 const double f = R.s0[k] * R.sp1[l];
                 const double2 hv = h[k * M + l];
-                const double2 c = ldc(t);
-                const double cr = c.x * f, ci = c.y * f;
-                ar += hv.x * cr - hv.y * ci;
-                ai += hv.x * ci + hv.y * cr;
+                const double cr = c[j].x * f, ci = c[j].y * f;
+                ++j;
+                ar = fma(hv.x, cr, ar);
+                ar = fma(-hv.y, ci, ar);
+                ai = fma(hv.x, ci, ai);
+                ai = fma(hv.y, cr, ai);
             }
-        }
     }
 
-    // double jumps: each removal pair (k <= s) present in the tile
+    // double jumps: one block of M*M*64 entries per pair present in the tile
     {
         int64_t off0, off1;
         t2_block(t2_off, tile, cap, off0, off1);
-        const __amdgpu_buffer_rsrc_t r2 = make_rsrc(t2 + off0, (uint32_t)((off1 - off0) * 4));
-        constexpr int W = (M * (M + 1) / 2 + 63) / 64;
-        const uint64_t *pm = pmask + tile * W;
-        int rank = 0;
-        if constexpr (MT <= 5) {
-            int p = 0;
-#pragma unroll
-            for (int k = 0; k < M; ++k) {
-#pragma unroll
-                for (int s = k; s < M; ++s, ++p) {
-                    if (!((pm[p >> 6] >> (p & 63)) & 1)) continue;
-                    pair_term<MT, BIGC>(M, k, s, p, rank, lane, n, R, r2, gp, ldc, ar, ai);
-                    ++rank;
-                }
-            }
-        } else {
-            int p = 0;
-            for (int k = 0; k < M; ++k) {
-                for (int s = k; s < M; ++s, ++p) {
-                    if (!((pm[p >> 6] >> (p & 63)) & 1)) continue;
-                    pair_term<MT, BIGC>(M, k, s, p, rank, lane, n, R, r2, gp, ldc, ar, ai);
-                    ++rank;
-                }
-            }
-        }
+        all_pairs<MT, BIGC>(std::make_integer_sequence<int, P>{}, pmask + tile * W, t2, off0, off1,
+                            lane, n, R, gp, ldc, ar, ai);
     }
     if (live) HC[g] = make_double2(ar, ai);
+}
+
+// ---------------------------------------------------------------------------
+// H.C without the double-jump map: a double jump (k, s) -> (q, l) is two
+// single jumps, first k -> q from the row, then s -> l from that
+// intermediate configuration,
+//     T2[g][(k,s)][q*M + l] = T1[T1[g][k][q]][s][l],
+// which holds for every valid removal pair (the intermediate still has a
+// particle in s).  The tile's single-jump rows stay in registers (they also
+// feed the one-body term); the second hop is a gather from rows near g.
+// ---------------------------------------------------------------------------
+template <int MT, bool BIGC, int P>
+__device__ __forceinline__ void pair_term_chained(int64_t D, const int32_t *__restrict__ t1,
+                                                  int lane, const int (&n)[MT],
+                                                  const Roots<MT> &R,
+                                                  const int32_t (&tr)[MT * MT],
+                                                  const double2 *__restrict__ gp,
+                                                  const Gather<BIGC> &ldc, double &ar,
+                                                  double &ai)
+{
+    constexpr int K = pair_k(MT, P), S = pair_s(MT, P);
+    constexpr int NS = MT * MT, SB = kSlotBatch<MT>;
+    const bool valid = K == S ? n[K] >= 2 : (n[K] >= 1 && n[S] >= 1);
+    if (!__ballot(valid)) return;   // no row of the tile can lose (K, S)
+    const double A = valid ? R.s0[K] * (K == S ? R.sm1[K] : R.s0[S]) : 0.0;
+    double rq[MT], dq[MT];
+#pragma unroll
+    for (int q = 0; q < MT; ++q) {
+        const int d = (q == K) + (q == S);
+        rq[q] = d == 0 ? R.sp1[q] : (d == 1 ? R.s0[q] : R.sm1[q]);
+        dq[q] = d == 0 ? R.sp2[q] : (d == 1 ? R.sp1[q] : R.s0[q]);
+    }
+    const double2 *G = gp + P * NS;
+    double br = 0.0, bi = 0.0;
+#pragma unroll
+    for (int j0 = 0; j0 < NS; j0 += SB) {
+        int32_t t[SB];
+        double2 c[SB];
+#pragma unroll
+        for (int i = 0; i < SB; ++i) {
+            const int j = j0 + i;
+            if (j >= NS) break;
+            const int q = j / MT, l = j % MT;
+            if (q == K) {
+                // first hop k -> k leaves the row unchanged
+                t[i] = valid ? tr[S * MT + l] : -1;
+            } else {
+                const int32_t b = tr[K * MT + q];
+                const bool ok = valid && b >= 0 && b < D;
+                const int64_t bb = ok ? b : 0;
+                const int32_t v = t1[((bb >> 6) * NS + S * MT + l) * kTile + (bb & 63)];
+                t[i] = ok ? v : -1;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < SB; ++i)
+            if (j0 + i < NS) c[i] = ldc(t[i]);
+#pragma unroll
+        for (int i = 0; i < SB; ++i) {
+            const int j = j0 + i;
+            if (j >= NS) break;
+            const int q = j / MT, l = j % MT;
+            const double B = q == l ? rq[q] * dq[q] : rq[q] * rq[l];
+            const double cr = c[i].x * B, ci = c[i].y * B;
+            const double2 Gv = G[j];
+            br = fma(Gv.x, cr, br);
+            br = fma(-Gv.y, ci, br);
+            bi = fma(Gv.x, ci, bi);
+            bi = fma(Gv.y, cr, bi);
+        }
+    }
+    ar = fma(A, br, ar);
+    ai = fma(A, bi, ai);
+}
+
+template <int MT, bool BIGC, int... Ps>
+__device__ __forceinline__ void all_pairs_chained(std::integer_sequence<int, Ps...>, int64_t D,
+                                                  const int32_t *__restrict__ t1, int lane,
+                                                  const int (&n)[MT], const Roots<MT> &R,
+                                                  const int32_t (&tr)[MT * MT],
+                                                  const double2 *__restrict__ gp,
+                                                  const Gather<BIGC> &ldc, double &ar,
+                                                  double &ai)
+{
+    (pair_term_chained<MT, BIGC, Ps>(D, t1, lane, n, R, tr, gp, ldc, ar, ai), ...);
+}
+
+// One 64-row tile of H.C through single jumps only (see above).
+template <int MT, typename OccT, bool BIGC>
+__device__ __forceinline__ void apply_tile_chained(int64_t tile, int64_t D,
+                                                   const OccT *__restrict__ occ,
+                                                   const int32_t *__restrict__ t1,
+                                                   const double2 *__restrict__ h,
+                                                   const double2 *__restrict__ gp,
+                                                   const double2 *__restrict__ C,
+                                                   double2 *__restrict__ HC)
+{
+    constexpr int M = MT;
+    constexpr int P = M * (M + 1) / 2;
+    const int lane = threadIdx.x & 63;
+    const int64_t g = tile * kTile + lane;
+    const bool live = g < D;
+    int n[M];
+    Roots<M> R;
+    load_row<MT, OccT>(occ, tile, M, lane, n, R);
+    const Gather<BIGC> ldc(C, D);
+    int32_t tr[M * M];
+    {
+        const __amdgpu_buffer_rsrc_t r1 =
+            make_rsrc(t1 + tile * M * M * kTile, (uint32_t)(M * M * kTile * 4));
+#pragma unroll
+        for (int j = 0; j < M * M; ++j) tr[j] = buf_ld_i32(r1, (uint32_t)((j * kTile + lane) * 4), 0);
+    }
+    const double2 cg = ldc(live ? (int32_t)g : -1);
+    double ar, ai;
+    {
+        double dr = 0.0, di = 0.0;
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const double2 hk = h[k * M + k];
+            dr = fma(hk.x, (double)n[k], dr);
+            di = fma(hk.y, (double)n[k], di);
+        }
+        ar = dr * cg.x - di * cg.y;
+        ai = dr * cg.y + di * cg.x;
+    }
+    {
+        constexpr int S1 = M * (M - 1);
+        double2 c[S1 > 0 ? S1 : 1];
+        int j = 0;
+#pragma unroll
+        for (int k = 0; k < M; ++k)
+#pragma unroll
+            for (int l = 0; l < M; ++l)
+                if (l != k) c[j++] = ldc(tr[k * M + l]);
+        j = 0;
+#pragma unroll
+        for (int k = 0; k < M; ++k)
+#pragma unroll
+            for (int l = 0; l < M; ++l) {
+                if (l == k) continue;
+                const double f = R.s0[k] * R.sp1[l];
+                const double2 hv = h[k * M + l];
+                const double cr = c[j].x * f, ci = c[j].y * f;
+                ++j;
+                ar = fma(hv.x, cr, ar);
+                ar = fma(-hv.y, ci, ar);
+                ai = fma(hv.x, ci, ai);
+                ai = fma(hv.y, cr, ai);
+            }
+    }
+    all_pairs_chained<MT, BIGC>(std::make_integer_sequence<int, P>{}, D, t1, lane, n, R, tr, gp,
+                                ldc, ar, ai);
+    if (live) HC[g] = make_double2(ar, ai);
+}
+
+template <int MT, typename OccT, bool BIGC>
+__global__ __launch_bounds__(256) void k_apply_chained(int64_t D, int64_t tiles, int64_t nblocks,
+                                                        const OccT *__restrict__ occ,
+                                                        const int32_t *__restrict__ t1,
+                                                        const double2 *__restrict__ h,
+                                                        const double2 *__restrict__ gp,
+                                                        const double2 *__restrict__ C,
+                                                        double2 *__restrict__ HC)
+{
+    const int64_t tile = xcd_block(blockIdx.x, nblocks) * 4 + wave_in_block();
+    if (tile >= tiles) return;
+    apply_tile_chained<MT, OccT, BIGC>(tile, D, occ, t1, h, gp, C, HC);
 }
 
 // H.C for any M (run-time orbital loops; the occupations and roots of each
@@ -358,7 +570,7 @@ __global__ __launch_bounds__(256) void k_rho1(int Mrt, int64_t D, int64_t tiles,
     constexpr int NA = (MA * MA + 63) / 64;
     const int M = MT > 0 ? MT : Mrt;
     const int lane = threadIdx.x & 63;
-    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int wave = blockIdx.x * 4 + wave_in_block();
     if (wave >= nwaves) return;
     double accr[NA], acci[NA];
 #pragma unroll (kUnroll<MT>)
@@ -576,11 +788,215 @@ __global__ __launch_bounds__(256) void k_zdotc_final(int nparts, const double2 *
         out[0] = make_double2((sr[0] + sr[1]) + (sr[2] + sr[3]), (si[0] + si[1]) + (si[2] + si[3]));
 }
 
+// out_i = scale * (op(a) op(x_i) + op(b) op(y_i)); op = conj where flagged;
+// a (b) NULL means 1, y NULL drops the second term.
+__global__ __launch_bounds__(256) void k_zaxpby(int64_t n, const double2 *__restrict__ a,
+                                                 const double2 *__restrict__ x,
+                                                 const double2 *__restrict__ b,
+                                                 const double2 *__restrict__ y, double scale,
+                                                 uint32_t flags, double2 *__restrict__ out)
+{
+    double2 A = a ? a[0] : make_double2(1.0, 0.0);
+    double2 B = b ? b[0] : make_double2(1.0, 0.0);
+    if (flags & MC_CONJ_A) A.y = -A.y;
+    if (flags & MC_CONJ_B) B.y = -B.y;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double2 xv = x[i];
+        if (flags & MC_CONJ_X) xv.y = -xv.y;
+        double rr = A.x * xv.x - A.y * xv.y, ri = A.x * xv.y + A.y * xv.x;
+        if (y) {
+            double2 yv = y[i];
+            if (flags & MC_CONJ_Y) yv.y = -yv.y;
+            rr += B.x * yv.x - B.y * yv.y;
+            ri += B.x * yv.y + B.y * yv.x;
+        }
+        out[i] = make_double2(scale * rr, scale * ri);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Lanczos building blocks with device-resident scalars.
+// ---------------------------------------------------------------------------
+constexpr int kGemvChunks = 64;
+
+// part[k][b] = sum over chunk b of conj(V_k,i) w_i
+__global__ __launch_bounds__(256) void k_zgemv_c_partial(int64_t n, const double2 *__restrict__ V,
+                                                          int64_t ldv,
+                                                          const double2 *__restrict__ w,
+                                                          double2 *__restrict__ part)
+{
+    __shared__ double sr[4], si[4];
+    const int k = blockIdx.y, b = blockIdx.x;
+    const int64_t chunk = (n + kGemvChunks - 1) / kGemvChunks;
+    const int64_t lo = b * chunk, hi = lo + chunk < n ? lo + chunk : n;
+    const double2 *v = V + (int64_t)k * ldv;
+    double ar = 0.0, ai = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        const double2 a = v[i], c = w[i];
+        ar += a.x * c.x + a.y * c.y;
+        ai += a.x * c.y - a.y * c.x;
+    }
+    ar = wave_sum(ar);
+    ai = wave_sum(ai);
+    if ((threadIdx.x & 63) == 0) {
+        sr[threadIdx.x >> 6] = ar;
+        si[threadIdx.x >> 6] = ai;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        part[(int64_t)k * kGemvChunks + b] =
+            make_double2((sr[0] + sr[1]) + (sr[2] + sr[3]), (si[0] + si[1]) + (si[2] + si[3]));
+}
+
+__global__ void k_zgemv_c_final(int K, const double2 *__restrict__ part, double2 *__restrict__ c)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    double sr = 0.0, si = 0.0;
+    for (int b = 0; b < kGemvChunks; ++b) {
+        sr += part[(int64_t)k * kGemvChunks + b].x;
+        si += part[(int64_t)k * kGemvChunks + b].y;
+    }
+    c[k] = make_double2(sr, si);
+}
+
+// w_i -= sum_k V_k,i c_k  (k in increasing order)
+__global__ __launch_bounds__(256) void k_zgemv_sub(int K, int64_t n, const double2 *__restrict__ V,
+                                                    int64_t ldv, const double2 *__restrict__ c,
+                                                    double2 *__restrict__ w)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double sr = 0.0, si = 0.0;
+        for (int k = 0; k < K; ++k) {
+            const double2 a = V[(int64_t)k * ldv + i], b = c[k];
+            sr += a.x * b.x - a.y * b.y;
+            si += a.x * b.y + a.y * b.x;
+        }
+        const double2 x = w[i];
+        w[i] = make_double2(x.x - sr, x.y - si);
+    }
+}
+
+// beta = sqrt(Re <w|w>) from a finished zdotc result; out = w / beta
+__global__ __launch_bounds__(256) void k_normalize(int64_t n, const double2 *__restrict__ dot,
+                                                   const double2 *__restrict__ w,
+                                                   double2 *__restrict__ out,
+                                                   double *__restrict__ beta)
+{
+    const double b = sqrt(dot[0].x);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && beta) beta[0] = b;
+    const double inv = b > 0.0 ? 1.0 / b : 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double2 x = w[i];
+        out[i] = make_double2(x.x * inv, x.y * inv);
+    }
+}
+
+// w -= Re(alpha) v + beta_prev v_prev (three-term Lanczos recurrence)
+__global__ __launch_bounds__(256) void k_lanczos_orth(int64_t n, double2 *__restrict__ w,
+                                                       const double2 *__restrict__ v,
+                                                       const double2 *__restrict__ vp,
+                                                       const double2 *__restrict__ alpha,
+                                                       const double *__restrict__ beta_prev)
+{
+    const double a = alpha[0].x;
+    const double b = (vp && beta_prev) ? beta_prev[0] : 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double2 x = w[i];
+        const double2 y = v[i];
+        x.x -= a * y.x;
+        x.y -= a * y.y;
+        if (b != 0.0) {
+            const double2 z = vp[i];
+            x.x -= b * z.x;
+            x.y -= b * z.y;
+        }
+        w[i] = x;
+    }
+}
+
 }  // namespace mc
 
 using namespace mc;
 
 extern "C" {
+
+int mc_lanczos_orth(int64_t n, double *w_d, const double *v_d, const double *vprev_d,
+                    const double *alpha_d, const double *beta_prev_d, mc_stream stream)
+{
+    if (n < 0 || (n > 0 && (!w_d || !v_d || !alpha_d))) return MC_EINVAL;
+    if (n == 0) return MC_OK;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_lanczos_orth, dim3(blocks), dim3(256), 0, (hipStream_t)stream, n,
+                       (double2 *)w_d, (const double2 *)v_d, (const double2 *)vprev_d,
+                       (const double2 *)alpha_d, beta_prev_d);
+    return launch_status();
+}
+
+int mc_zgemv_c(int32_t K, int64_t n, const double *V_d, int64_t ldv, const double *w_d,
+               double *c_d, void *ws_d, size_t ws_bytes, mc_stream stream)
+{
+    if (K < 0 || n < 0 || ldv < n) return MC_EINVAL;
+    if (K == 0) return MC_OK;
+    if (!V_d || !w_d || !c_d || !ws_d) return MC_EINVAL;
+    if (ws_bytes < (size_t)K * kGemvChunks * 16) return MC_ENOMEM;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_zgemv_c_partial, dim3(kGemvChunks, K), dim3(256), 0, s, n,
+                       (const double2 *)V_d, ldv, (const double2 *)w_d, (double2 *)ws_d);
+    hipLaunchKernelGGL(k_zgemv_c_final, dim3((K + 255) / 256), dim3(256), 0, s, K,
+                       (const double2 *)ws_d, (double2 *)c_d);
+    return launch_status();
+}
+
+int mc_zgemv_sub(int32_t K, int64_t n, const double *V_d, int64_t ldv, const double *c_d,
+                 double *w_d, mc_stream stream)
+{
+    if (K < 0 || n < 0 || ldv < n) return MC_EINVAL;
+    if (K == 0 || n == 0) return MC_OK;
+    if (!V_d || !w_d || !c_d) return MC_EINVAL;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_zgemv_sub, dim3(blocks), dim3(256), 0, (hipStream_t)stream, K, n,
+                       (const double2 *)V_d, ldv, (const double2 *)c_d, (double2 *)w_d);
+    return launch_status();
+}
+
+int mc_normalize(int64_t n, const double *w_d, double *out_d, double *beta_d, void *ws_d,
+                 size_t ws_bytes, mc_stream stream)
+{
+    if (n < 0 || !w_d || !out_d || !ws_d) return MC_EINVAL;
+    if (ws_bytes < (size_t)(MC_DOT_BLOCKS + 2) * 16) return MC_ENOMEM;
+    hipStream_t s = (hipStream_t)stream;
+    double2 *part = (double2 *)ws_d;
+    double2 *dot = part + MC_DOT_BLOCKS + 1;
+    hipLaunchKernelGGL(k_zdotc_partial, dim3(MC_DOT_BLOCKS), dim3(256), 0, s, n,
+                       (const double2 *)w_d, (const double2 *)w_d, part);
+    hipLaunchKernelGGL(k_zdotc_final, dim3(1), dim3(256), 0, s, MC_DOT_BLOCKS, part, dot);
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_normalize, dim3(blocks), dim3(256), 0, s, n, dot, (const double2 *)w_d,
+                       (double2 *)out_d, beta_d);
+    return launch_status();
+}
+
+int mc_zaxpby(int64_t n, const double *a_d, const double *x_d, const double *b_d,
+              const double *y_d, double scale, uint32_t flags, double *out_d, mc_stream stream)
+{
+    if (n < 0 || (n > 0 && (!x_d || !out_d))) return MC_EINVAL;
+    if (n == 0) return MC_OK;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_zaxpby, dim3(blocks), dim3(256), 0, (hipStream_t)stream, n,
+                       (const double2 *)a_d, (const double2 *)x_d, (const double2 *)b_d,
+                       (const double2 *)y_d, scale, flags, (double2 *)out_d);
+    return launch_status();
+}
 
 int mc_workspace_size(int32_t N, int32_t M, int32_t op, size_t *bytes)
 {
@@ -592,7 +1008,7 @@ int mc_workspace_size(int32_t N, int32_t M, int32_t op, size_t *bytes)
     const int64_t tiles = (D + kTile - 1) / kTile;
     const int64_t P = npairs(M);
     switch (op) {
-    case MC_OP_APPLY: *bytes = (size_t)(P * M * M * 16); return MC_OK;
+    case MC_OP_APPLY: *bytes = (size_t)((P * M * M + M * M) * 16); return MC_OK;
     case MC_OP_RHO1: *bytes = (size_t)rho_waves(tiles) * M * M * 16; return MC_OK;
     case MC_OP_RHO2: *bytes = (size_t)rho_waves(tiles) * P * M * M * 16; return MC_OK;
     case MC_OP_DOT: *bytes = (size_t)(MC_DOT_BLOCKS + 1) * 16; return MC_OK;
@@ -600,12 +1016,14 @@ int mc_workspace_size(int32_t N, int32_t M, int32_t op, size_t *bytes)
     }
 }
 
-int mc_apply_H(int32_t N, int32_t M, const double *h_d, const double *g_d, const mc_tables *t,
-               const double *C_d, double *HC_d, void *ws_d, size_t ws_bytes, mc_stream stream)
+static int apply_common(int32_t N, int32_t M, const double *h_d, const double *g_d,
+                        const mc_tables *t, const double *C_d, double *HC_d, void *ws_d,
+                        size_t ws_bytes, int adjoint, mc_stream stream)
 {
     int st = check_nm(N, M);
     if (st) return st;
-    st = check_tables(N, M, t, true);
+    const bool chained = t && t->t2_d == nullptr;   // no double-jump map: chain single jumps
+    st = check_tables(N, M, t, !chained);
     if (st) return st;
     if (!h_d || !g_d || !C_d || !HC_d || !ws_d) return MC_EINVAL;
     const int64_t D = t->dim;
@@ -613,33 +1031,60 @@ int mc_apply_H(int32_t N, int32_t M, const double *h_d, const double *g_d, const
     size_t need = 0;
     mc_workspace_size(N, M, MC_OP_APPLY, &need);
     if (ws_bytes < need) return MC_ENOMEM;
-    if (M > 8 && (size_t)5 * M * kTile * 8 > 65536) return MC_EINVAL;   // generic kernel: M <= 25
+    if (M > 8 && (chained || (size_t)5 * M * kTile * 8 > 65536)) return MC_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     double2 *gp = (double2 *)ws_d;
-    hipLaunchKernelGGL(k_gprime, dim3(4), dim3(256), 0, s, M, (const double2 *)g_d, gp);
+    double2 *hp = gp + (size_t)npairs(M) * M * M;
+    hipLaunchKernelGGL(k_prep, dim3(4), dim3(256), 0, s, M, adjoint, (const double2 *)g_d,
+                       (const double2 *)h_d, gp, hp);
     const int64_t nblocks = (t->tiles + 3) / 4;
     const bool big = D * 16 > (int64_t)0xFFFFFFFFu;
 #define MC_APPLY_LAUNCH(OT, BIG)                                                               \
     if (M <= 8) {                                                                              \
         MC_DISPATCH_M(M, if constexpr (MT > 0) hipLaunchKernelGGL(                              \
                              (k_apply<MT, OT, BIG>), dim3(nblocks), dim3(256), 0, s, D,         \
-                             t->tiles, nblocks, t->t2_entries, (const OT *)t->occ_d, t->t1_d, t->pmask_d,      \
-                             t->t2_off_d, t->t2_d, (const double2 *)h_d, (const double2 *)gp,   \
-                             (const double2 *)C_d, (double2 *)HC_d));                          \
+                             t->tiles, nblocks, t->t2_entries, (const OT *)t->occ_d, t->t1_d,   \
+                             t->pmask_d, t->t2_off_d, t->t2_d, (const double2 *)hp,             \
+                             (const double2 *)gp, (const double2 *)C_d, (double2 *)HC_d));     \
     } else {                                                                                   \
         hipLaunchKernelGGL((k_apply_generic<OT, BIG>), dim3(t->tiles), dim3(64),                \
                            (size_t)5 * M * kTile * 8, s, M, D, t->tiles, t->t2_entries,        \
-                           (const OT *)t->occ_d,  \
-                           t->t1_d, t->pmask_d, t->t2_off_d, t->t2_d, (const double2 *)h_d,     \
-                           (const double2 *)gp, (const double2 *)C_d, (double2 *)HC_d);        \
+                           (const OT *)t->occ_d, t->t1_d, t->pmask_d, t->t2_off_d, t->t2_d,    \
+                           (const double2 *)hp, (const double2 *)gp, (const double2 *)C_d,     \
+                           (double2 *)HC_d);                                                   \
     }
-    if (occ_width(N) == 1) {
+#define MC_CHAINED_LAUNCH(OT, BIG)                                                             \
+    MC_DISPATCH_M(M, if constexpr (MT > 0) hipLaunchKernelGGL(                                  \
+                         (k_apply_chained<MT, OT, BIG>), dim3(nblocks), dim3(256), 0, s, D,     \
+                         t->tiles, nblocks, (const OT *)t->occ_d, t->t1_d, (const double2 *)hp, \
+                         (const double2 *)gp, (const double2 *)C_d, (double2 *)HC_d))
+    if (chained) {
+        if (occ_width(N) == 1) {
+            if (big) { MC_CHAINED_LAUNCH(uint8_t, true); } else { MC_CHAINED_LAUNCH(uint8_t, false); }
+        } else {
+            if (big) { MC_CHAINED_LAUNCH(uint16_t, true); } else { MC_CHAINED_LAUNCH(uint16_t, false); }
+        }
+    } else if (occ_width(N) == 1) {
         if (big) { MC_APPLY_LAUNCH(uint8_t, true); } else { MC_APPLY_LAUNCH(uint8_t, false); }
     } else {
         if (big) { MC_APPLY_LAUNCH(uint16_t, true); } else { MC_APPLY_LAUNCH(uint16_t, false); }
     }
+#undef MC_CHAINED_LAUNCH
 #undef MC_APPLY_LAUNCH
     return launch_status();
+}
+
+int mc_apply_H(int32_t N, int32_t M, const double *h_d, const double *g_d, const mc_tables *t,
+               const double *C_d, double *HC_d, void *ws_d, size_t ws_bytes, mc_stream stream)
+{
+    return apply_common(N, M, h_d, g_d, t, C_d, HC_d, ws_d, ws_bytes, 0, stream);
+}
+
+int mc_apply_H_adjoint(int32_t N, int32_t M, const double *h_d, const double *g_d,
+                       const mc_tables *t, const double *C_d, double *HC_d, void *ws_d,
+                       size_t ws_bytes, mc_stream stream)
+{
+    return apply_common(N, M, h_d, g_d, t, C_d, HC_d, ws_d, ws_bytes, 1, stream);
 }
 
 int mc_rho1(int32_t N, int32_t M, const mc_tables *t, const double *C_d, double *rho1_d,

@@ -51,7 +51,7 @@ __global__ __launch_bounds__(256) void k_build_index(int N, int Mrt, int64_t D, 
     constexpr int MA = MT > 0 ? MT : MC_MAX_M;
     const int M = MT > 0 ? MT : Mrt;
     const int lane = threadIdx.x & 63;
-    const int64_t tile = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t tile = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave_in_block();
     if (tile >= tiles) return;   // uniform per wavefront
     const int64_t g = tile * kTile + lane;
     int n[MA];
@@ -155,7 +155,7 @@ __global__ __launch_bounds__(256) void k_build_t2(int N, int Mrt, int64_t tiles,
     constexpr int MA = MT > 0 ? MT : MC_MAX_M;
     const int M = MT > 0 ? MT : Mrt;
     const int lane = threadIdx.x & 63;
-    const int64_t tile = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t tile = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave_in_block();
     if (tile >= tiles) return;
     int n[MA], w[MA];
 #pragma unroll (kUnroll<MT>)

@@ -129,7 +129,7 @@ def test_tables_size(lib):
 
 def test_workspace_size(lib):
     import paper_2005_13679_amd as mc
-    assert mc.workspace_size(10, 5, 1) == 15 * 25 * 16
+    assert mc.workspace_size(10, 5, 1) == (15 * 25 + 25) * 16
     assert mc.workspace_size(10, 5, 2) > 0 and mc.workspace_size(10, 5, 3) > 0
     b = ctypes.c_size_t()
     assert lib.mc_workspace_size(10, 5, 99, ctypes.byref(b)) == -1

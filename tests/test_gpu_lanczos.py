@@ -1,0 +1,68 @@
+"""GPU Lanczos (Sec. VI) against the oracle's Lanczos and the Bethe ansatz."""
+
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import bethe
+from oracle.lanczos import lanczos_ground, lanczos_recurrence
+from tests.conftest import GOLDEN
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def test_small_matches_oracle_lanczos(mc, oracle_native):
+    from paper_2005_13679_amd import lanczos
+    N, M, c = 5, 11, 10.0        # the paper's 11 plane waves, 5 bosons
+    h, g = W.lieb_liniger_h(M), W.lieb_liniger_g(M, c)
+    tab = mc.build_tables(N, M)
+    v0 = W.random_coefficients(np.random.default_rng(1), tab.dim)
+    e_gpu, *_ = lanczos.ground_state(h, g, tab, dev(v0), max_iter=300, tol=1e-13)
+    e_orc, *_ = lanczos_ground(lambda v: oracle_native.apply_h(N, M, h, g, v), v0, max_iter=300,
+                               tol=1e-13, res_tol=1e-10)
+    assert abs(e_gpu - e_orc) <= 1e-9 * abs(e_orc)
+    assert e_gpu >= bethe.ground_energy(N, c) - 1e-9
+
+
+def test_three_term_recurrence_matches_oracle(mc, oracle_native):
+    from paper_2005_13679_amd import lanczos
+    N, M = 10, 5
+    C, h, g = W.random_instance(N, M, 0)
+    tab = mc.build_tables(N, M)
+    v0 = W.random_coefficients(np.random.default_rng(4), tab.dim)
+    _, a, b, it = lanczos.ground_state(h, g, tab, dev(v0), max_iter=20, tol=0.0,
+                                       reorthogonalize=False)
+    a2, b2 = lanczos_recurrence(lambda v: oracle_native.apply_h(N, M, h, g, v), v0, 20)
+    assert np.allclose(a, a2, rtol=1e-10, atol=1e-10)
+    assert np.allclose(b[: len(a) - 1], b2[: len(a) - 1], rtol=1e-10, atol=1e-10)
+
+
+def test_lieb_liniger_workload():
+    """N = 20, plane waves up to M = 7 (dim 230,230): GPU Lanczos equals the
+    oracle's stored energies; variational and monotone in M."""
+    import paper_2005_13679_amd as mc
+    from paper_2005_13679_amd import lanczos
+    path = os.path.join(GOLDEN, "ll_energies.json")
+    ref = json.load(open(path))
+    N, L = ref["N"], ref["L"]
+    by_gamma = {}
+    for r in ref["runs"]:
+        M = r["M"]
+        h, g = W.lieb_liniger_h(M, L), W.lieb_liniger_g(M, r["c"], L)
+        tab = mc.build_tables(N, M)
+        v0 = W.random_coefficients(np.random.default_rng(1000 + M), tab.dim)
+        e, *_ = lanczos.ground_state(h, g, tab, dev(v0), max_iter=400, tol=1e-13)
+        assert abs(e - r["E0"]) <= 1e-9 * abs(r["E0"]), (r, e)
+        assert e >= r["E_bethe"] - 1e-9
+        by_gamma.setdefault(r["gamma"], []).append((M, e))
+    for gamma, lst in by_gamma.items():
+        es = [e for _, e in sorted(lst)]
+        assert all(b <= a + 1e-9 for a, b in zip(es, es[1:])), gamma
