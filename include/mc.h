@@ -233,6 +233,68 @@ int mc_zaxpby(int64_t n, const double *a_d, const double *x_d, const double *b_d
               const double *y_d, double scale, uint32_t flags, double *out_d, mc_stream stream);
 
 /* ------------------------------------------------------------------------ */
+/* Batches of instances of uneven size                                      */
+/* ------------------------------------------------------------------------ */
+/*
+ * A batch applies H_i to C_i for many instances i = (N_i, M_i, h_i, g_i) at
+ * once.  A batch vector is the concatenation of the instances' coefficient
+ * vectors in the order the caller lists them (instance i at offset
+ * sum_{j<i} D_j, total mc_batch_vector_length()).  Instances are grouped by
+ * orbital count; each group runs as one persistent kernel whose wavefronts
+ * walk the group's (instance, 64-row tile) work list.  An instance whose
+ * tables hold a double-jump map uses it; one built without it (t2_d == NULL)
+ * chains two single jumps.  Limits per instance: M <= 8, N <= 255, D < 2^28.
+ *
+ * Every batch call only enqueues kernels on `stream` (no host
+ * synchronisation, no memset), so sequences of calls can be captured into a
+ * HIP graph and replayed.
+ */
+typedef struct mc_batch_item {
+    const mc_tables *tables;     /* host pointer to built tables of the instance */
+    const double *h_d, *g_d;     /* h [M*M], g [M^4] complex128, device; read at each apply */
+} mc_batch_item;
+
+typedef struct mc_batch_schedule {
+    int32_t blocks_per_cu;   /* persistent grid per group: blocks_per_cu x CUs blocks of
+                                256 threads (0 = 2) */
+    int32_t order;           /* 0: wavefront w takes work items w, w+W, ...; 1: each
+                                wavefront takes a contiguous range of items */
+    int32_t reserved[2];
+} mc_batch_schedule;
+
+typedef struct mc_batch mc_batch;   /* opaque host handle */
+
+/* Bytes of the device plan buffer mc_batch_create needs. */
+int mc_batch_plan_size(int32_t count, const mc_batch_item *items, size_t *bytes);
+
+/* Builds the plan into plan_d (caller-owned device memory, plan_bytes >=
+ * mc_batch_plan_size) and returns a host handle in *out (free with
+ * mc_batch_destroy).  Synchronises `stream` once (plan upload).  The tables
+ * and h/g buffers must outlive the handle. */
+int mc_batch_create(int32_t count, const mc_batch_item *items, const mc_batch_schedule *sched,
+                    void *plan_d, size_t plan_bytes, mc_stream stream, mc_batch **out);
+int mc_batch_destroy(mc_batch *b);
+int64_t mc_batch_vector_length(const mc_batch *b);
+
+/* HC_d = H_i C_d per instance segment (batch vectors, no overlap). */
+int mc_batch_apply_H(const mc_batch *b, const double *C_d, double *HC_d, mc_stream stream);
+
+/* out_d[i] = <x_i | y_i> (complex128 per instance, caller order), fixed-order
+ * reductions. */
+int mc_batch_dot(const mc_batch *b, const double *x_d, const double *y_d, double *out_d,
+                 mc_stream stream);
+
+/* Per instance: w_i -= Re(alpha_d[i]) v_i + beta_d[i] vprev_i (alpha complex128,
+ * beta double; vprev_d or beta_d NULL drops the second term). */
+int mc_batch_lanczos_orth(const mc_batch *b, double *w_d, const double *v_d,
+                          const double *vprev_d, const double *alpha_d, const double *beta_d,
+                          mc_stream stream);
+
+/* Per instance: beta_d[i] = ||w_i||, out_i = w_i / beta_d[i] (0 if beta = 0). */
+int mc_batch_normalize(const mc_batch *b, const double *w_d, double *out_d, double *beta_d,
+                       mc_stream stream);
+
+/* ------------------------------------------------------------------------ */
 /* Lanczos building blocks (Sec. VI: Lanczos tridiagonalisation with full   */
 /* reorthogonalisation).  Scalars stay on the device.                        */
 /* ------------------------------------------------------------------------ */

@@ -100,6 +100,27 @@ SIGNATURES = {
 }
 
 
+class BatchItem(ctypes.Structure):
+    _fields_ = [("tables", ctypes.POINTER(CTables)), ("h_d", c_p), ("g_d", c_p)]
+
+
+class BatchSchedule(ctypes.Structure):
+    _fields_ = [("blocks_per_cu", c_i32), ("order", c_i32), ("reserved", c_i32 * 2)]
+
+
+SIGNATURES.update({
+    "mc_batch_plan_size": (ctypes.c_int, [c_i32, ctypes.POINTER(BatchItem), ctypes.POINTER(c_sz)]),
+    "mc_batch_create": (ctypes.c_int, [c_i32, ctypes.POINTER(BatchItem), ctypes.POINTER(BatchSchedule),
+                                       c_p, c_sz, c_p, ctypes.POINTER(c_p)]),
+    "mc_batch_destroy": (ctypes.c_int, [c_p]),
+    "mc_batch_vector_length": (c_i64, [c_p]),
+    "mc_batch_apply_H": (ctypes.c_int, [c_p, c_p, c_p, c_p]),
+    "mc_batch_dot": (ctypes.c_int, [c_p, c_p, c_p, c_p, c_p]),
+    "mc_batch_lanczos_orth": (ctypes.c_int, [c_p, c_p, c_p, c_p, c_p, c_p, c_p]),
+    "mc_batch_normalize": (ctypes.c_int, [c_p, c_p, c_p, c_p, c_p]),
+})
+
+
 class MCError(RuntimeError):
     def __init__(self, status: int, where: str):
         lib = _lib

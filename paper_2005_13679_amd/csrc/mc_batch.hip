@@ -1,0 +1,492 @@
+// Batched H.C over many (N, M, h, g) instances of uneven size, and the
+// segmented vector operations a batched Lanczos recurrence needs.
+//
+// A batch vector is the concatenation of the instances' coefficient vectors
+// (instance i at offset vec_off[i]).  The plan, built once into a caller
+// buffer, holds per-instance descriptors and staged coefficients, the
+// instances grouped by orbital count, and a chunk table for segmented
+// reductions.  Each group runs as one persistent kernel: its wavefronts walk
+// the group's (instance, tile) work list, so instances of 45 rows and of
+// 6*10^7 rows share the same launch.  Every call only enqueues kernels (no
+// host synchronisation, no memset), so a sequence of calls can be captured
+// into a HIP graph and replayed.
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
+#include "mc_apply.h"
+#include "mc_internal.h"
+
+namespace mc {
+
+struct BatchInst {
+    int32_t N, M;
+    int64_t dim, tiles, cap, vec_off;
+    const uint8_t *occ;
+    const int32_t *t1;
+    const uint64_t *pmask;
+    const int64_t *t2_off;
+    const int32_t *t2;   // null: chain single jumps
+    const double2 *h, *g;
+    double2 *hp, *gp;    // staged h' and G'
+};
+
+struct BatchChunk {
+    int32_t inst;
+    int32_t pad;
+    int64_t start, len;   // in batch-vector elements
+};
+
+constexpr int64_t kChunk = 1 << 16;
+
+}  // namespace mc
+
+struct mc_batch {
+    int32_t count;
+    int32_t ngroups;
+    int32_t group_M[8];
+    int32_t group_first[8];   // first entry in the sorted instance order
+    int32_t group_count[8];
+    int64_t group_tiles[8];
+    int64_t group_blocks[8];
+    int64_t nchunks;
+    int64_t total_len;        // batch-vector length
+    int32_t order;
+    mc::BatchInst *inst_d;    // [count], in sorted order
+    int64_t *tile_prefix_d;   // [count + 1] per sorted instance, restarting per group
+    mc::BatchChunk *chunks_d; // [nchunks]
+    double2 *partials_d;      // [nchunks]
+    int32_t *sorted_d;        // [count] sorted position -> caller index
+    int32_t *pos_d;           // [count] caller index -> sorted position
+};
+
+namespace mc {
+
+__global__ void k_batch_prep(const BatchInst *__restrict__ inst)
+{
+    const BatchInst I = inst[blockIdx.y];
+    const int M = I.M;
+    const int P = M * (M + 1) / 2;
+    const int total = P * M * M;
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total + M * M;
+         idx += gridDim.x * blockDim.x) {
+        if (idx >= total) {
+            const int e = idx - total;
+            I.hp[e] = I.h[e];
+            continue;
+        }
+        const int p = idx / (M * M), ql = idx % (M * M);
+        int k = 0, rem = p;
+        while (rem >= M - k) {
+            rem -= M - k;
+            ++k;
+        }
+        const int s = k + rem;
+        const int q = ql / M, l = ql % M;
+        double2 a = I.g[((k * M + s) * M + q) * M + l];
+        if (k != s) {
+            const double2 b = I.g[((s * M + k) * M + q) * M + l];
+            a.x += b.x;
+            a.y += b.y;
+        }
+        I.gp[idx] = make_double2(0.5 * a.x, 0.5 * a.y);
+    }
+}
+
+// Persistent H.C over one orbital-count group.  Work item i of the group is
+// tile (i - prefix[j]) of the group's j-th instance; with order 0 wavefront w
+// takes items w, w + W, w + 2W, ... (neighbouring tiles on neighbouring
+// wavefronts), with order 1 a contiguous range of items.
+template <int MT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MC_APPLY_WAVES)))
+void k_batch_apply(const BatchInst *__restrict__ inst, const int64_t *__restrict__ prefix,
+                   int first, int count, int64_t items, int64_t nblocks, int order,
+                   const double2 *__restrict__ Cb, double2 *__restrict__ HCb)
+{
+    const int64_t W = nblocks * 4;
+    const int64_t w = xcd_block(blockIdx.x, nblocks) * 4 + wave_in_block();
+    const int64_t per = (items + W - 1) / W;
+    const int64_t i0 = order == 0 ? w : w * per;
+    const int64_t step = order == 0 ? W : 1;
+    const int64_t iend = order == 0 ? items : (i0 + per < items ? i0 + per : items);
+    int j = 0;
+    for (int64_t i = i0; i < iend; i += step) {
+        // instance of item i (prefix is non-decreasing; items are visited in
+        // increasing order so the search resumes where it stopped)
+        while (j + 1 < count && prefix[first + j + 1] <= i) ++j;
+        const BatchInst I = inst[first + j];
+        const int64_t tile = i - prefix[first + j];
+        const double2 *C = Cb + I.vec_off;
+        double2 *HC = HCb + I.vec_off;
+        if (I.t2)
+            apply_tile_t2<MT, uint8_t, false>(tile, I.dim, I.cap, I.occ, I.t1, I.pmask, I.t2_off,
+                                              I.t2, I.hp, I.gp, C, HC);
+        else
+            apply_tile_chained<MT, uint8_t, false>(tile, I.dim, I.occ, I.t1, I.hp, I.gp, C, HC);
+    }
+}
+
+// Segmented conj(x).y: chunk partials, then per-instance sums in chunk order.
+__global__ __launch_bounds__(256) void k_seg_dot_partial(const BatchChunk *__restrict__ ch,
+                                                          int64_t nchunks,
+                                                          const double2 *__restrict__ x,
+                                                          const double2 *__restrict__ y,
+                                                          double2 *__restrict__ part)
+{
+    __shared__ double sr[4], si[4];
+    for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const BatchChunk C = ch[c];
+        double ar = 0.0, ai = 0.0;
+        for (int64_t i = C.start + threadIdx.x; i < C.start + C.len; i += blockDim.x) {
+            const double2 a = x[i], b = y[i];
+            ar += a.x * b.x + a.y * b.y;
+            ai += a.x * b.y - a.y * b.x;
+        }
+        ar = wave_sum(ar);
+        ai = wave_sum(ai);
+        if ((threadIdx.x & 63) == 0) {
+            sr[wave_in_block()] = ar;
+            si[wave_in_block()] = ai;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0)
+            part[c] = make_double2((sr[0] + sr[1]) + (sr[2] + sr[3]), (si[0] + si[1]) + (si[2] + si[3]));
+        __syncthreads();
+    }
+}
+
+// out[caller index] = sum of the instance's chunk partials (chunks of an
+// instance are contiguous and in order); sqrt_real: write sqrt(Re) as double.
+__global__ void k_seg_final(const BatchChunk *__restrict__ ch, int64_t nchunks, int count,
+                            const int32_t *__restrict__ sorted, const double2 *__restrict__ part,
+                            double2 *__restrict__ out_c, double *__restrict__ out_norm)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= count) return;
+    // binary search for the first chunk of sorted instance j
+    int64_t lo = 0, hi = nchunks;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (ch[mid].inst < j) lo = mid + 1;
+        else hi = mid;
+    }
+    double sr = 0.0, si = 0.0;
+    for (int64_t c = lo; c < nchunks && ch[c].inst == j; ++c) {
+        sr += part[c].x;
+        si += part[c].y;
+    }
+    const int dst = sorted[j];
+    if (out_c) out_c[dst] = make_double2(sr, si);
+    if (out_norm) out_norm[dst] = sqrt(sr);
+}
+
+// w -= Re(alpha_i) v + beta_i v_prev per instance segment (three-term step)
+__global__ __launch_bounds__(256) void k_seg_orth(const BatchChunk *__restrict__ ch,
+                                                   int64_t nchunks,
+                                                   const int32_t *__restrict__ sorted,
+                                                   double2 *__restrict__ w,
+                                                   const double2 *__restrict__ v,
+                                                   const double2 *__restrict__ vp,
+                                                   const double2 *__restrict__ alpha,
+                                                   const double *__restrict__ beta)
+{
+    for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const BatchChunk C = ch[c];
+        const int dst = sorted[C.inst];
+        const double a = alpha[dst].x;
+        const double b = (vp && beta) ? beta[dst] : 0.0;
+        for (int64_t i = C.start + threadIdx.x; i < C.start + C.len; i += blockDim.x) {
+            double2 x = w[i];
+            const double2 y = v[i];
+            x.x -= a * y.x;
+            x.y -= a * y.y;
+            if (b != 0.0) {
+                const double2 z = vp[i];
+                x.x -= b * z.x;
+                x.y -= b * z.y;
+            }
+            w[i] = x;
+        }
+    }
+}
+
+// out = w / beta_i per instance segment (0 where beta_i = 0)
+__global__ __launch_bounds__(256) void k_seg_scale(const BatchChunk *__restrict__ ch,
+                                                    int64_t nchunks,
+                                                    const int32_t *__restrict__ sorted,
+                                                    const double2 *__restrict__ w,
+                                                    const double *__restrict__ beta,
+                                                    double2 *__restrict__ out)
+{
+    for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const BatchChunk C = ch[c];
+        const double b = beta[sorted[C.inst]];
+        const double inv = b > 0.0 ? 1.0 / b : 0.0;
+        for (int64_t i = C.start + threadIdx.x; i < C.start + C.len; i += blockDim.x) {
+            const double2 x = w[i];
+            out[i] = make_double2(x.x * inv, x.y * inv);
+        }
+    }
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct PlanLayout {
+    size_t inst, prefix, chunks, partials, sorted, pos, coef, total;
+};
+
+static int plan_layout(int32_t count, const mc_batch_item *items, int64_t *nchunks_out,
+                       int64_t *coef_elems_out, PlanLayout *L)
+{
+    int64_t nchunks = 0, coef = 0;
+    for (int i = 0; i < count; ++i) {
+        const mc_tables *t = items[i].tables;
+        if (!t) return MC_EINVAL;
+        const int M = t->M;
+        nchunks += (t->dim + kChunk - 1) / kChunk;
+        coef += (int64_t)npairs(M) * M * M + (int64_t)M * M;
+    }
+    L->inst = 0;
+    L->prefix = align256(L->inst + sizeof(BatchInst) * count);
+    L->chunks = align256(L->prefix + sizeof(int64_t) * (count + 1));
+    L->partials = align256(L->chunks + sizeof(BatchChunk) * nchunks);
+    L->sorted = align256(L->partials + sizeof(double2) * nchunks);
+    L->pos = align256(L->sorted + sizeof(int32_t) * count);
+    L->coef = align256(L->pos + sizeof(int32_t) * count);
+    L->total = align256(L->coef + sizeof(double2) * coef);
+    *nchunks_out = nchunks;
+    *coef_elems_out = coef;
+    return MC_OK;
+}
+
+}  // namespace mc
+
+using namespace mc;
+
+extern "C" {
+
+int mc_batch_plan_size(int32_t count, const mc_batch_item *items, size_t *bytes)
+{
+    if (count < 1 || !items || !bytes) return MC_EINVAL;
+    PlanLayout L;
+    int64_t nch, coef;
+    const int st = plan_layout(count, items, &nch, &coef, &L);
+    if (st) return st;
+    *bytes = L.total;
+    return MC_OK;
+}
+
+int mc_batch_create(int32_t count, const mc_batch_item *items, const mc_batch_schedule *sched,
+                    void *plan_d, size_t plan_bytes, mc_stream stream, mc_batch **out)
+{
+    if (count < 1 || !items || !out || !plan_d) return MC_EINVAL;
+    *out = nullptr;
+    for (int i = 0; i < count; ++i) {
+        const mc_tables *t = items[i].tables;
+        if (!t || !items[i].h_d || !items[i].g_d) return MC_EINVAL;
+        int st = check_nm(t->N, t->M);
+        if (st) return st;
+        st = check_tables(t->N, t->M, t, t->t2_d != nullptr);
+        if (st) return st;
+        // batched instances: M <= 8, N <= 255, D < 2^28 (range-checked gathers)
+        if (t->M > 8 || occ_width(t->N) != 1 || t->dim * 16 > (int64_t)0xFFFFFFFFu) return MC_EINVAL;
+    }
+    PlanLayout L;
+    int64_t nchunks, coef_elems;
+    int st = plan_layout(count, items, &nchunks, &coef_elems, &L);
+    if (st) return st;
+    if (plan_bytes < L.total) return MC_ENOMEM;
+    const int bpc = sched && sched->blocks_per_cu > 0 ? sched->blocks_per_cu : 2;
+    const int order = sched ? sched->order : 0;
+    if (order != 0 && order != 1) return MC_EINVAL;
+
+    // instance order: by orbital count, then decreasing dimension
+    std::vector<int32_t> sorted(count);
+    std::iota(sorted.begin(), sorted.end(), 0);
+    std::stable_sort(sorted.begin(), sorted.end(), [&](int a, int b) {
+        const mc_tables *x = items[a].tables, *y = items[b].tables;
+        if (x->M != y->M) return x->M < y->M;
+        return x->dim > y->dim;
+    });
+    mc_batch *b = (mc_batch *)calloc(1, sizeof(mc_batch));
+    if (!b) return MC_ENOMEM;
+    b->count = count;
+    b->order = order;
+    std::vector<int32_t> pos(count);
+    std::vector<BatchInst> inst(count);
+    std::vector<int64_t> prefix(count + 1, 0);
+    std::vector<BatchChunk> chunks;
+    chunks.reserve(nchunks);
+    char *base = (char *)plan_d;
+    double2 *coef = (double2 *)(base + L.coef);
+    int64_t voff = 0, cpos = 0;
+    for (int j = 0; j < count; ++j) {
+        const int i = sorted[j];
+        pos[i] = j;
+        const mc_tables *t = items[i].tables;
+        BatchInst &I = inst[j];
+        I.N = t->N;
+        I.M = t->M;
+        I.dim = t->dim;
+        I.tiles = t->tiles;
+        I.cap = t->t2_d ? t->t2_entries : 0;
+        I.vec_off = 0;
+        I.occ = (const uint8_t *)t->occ_d;
+        I.t1 = t->t1_d;
+        I.pmask = t->pmask_d;
+        I.t2_off = t->t2_off_d;
+        I.t2 = t->t2_d;
+        I.h = (const double2 *)items[i].h_d;
+        I.g = (const double2 *)items[i].g_d;
+        I.gp = coef + cpos;
+        cpos += (int64_t)npairs(t->M) * t->M * t->M;
+        I.hp = coef + cpos;
+        cpos += (int64_t)t->M * t->M;
+        // group bookkeeping
+        if (b->ngroups == 0 || b->group_M[b->ngroups - 1] != t->M) {
+            b->group_M[b->ngroups] = t->M;
+            b->group_first[b->ngroups] = j;
+            b->group_count[b->ngroups] = 0;
+            b->group_tiles[b->ngroups] = 0;
+            ++b->ngroups;
+        }
+        const int gi = b->ngroups - 1;
+        prefix[j] = b->group_tiles[gi];
+        b->group_tiles[gi] += t->tiles;
+        ++b->group_count[gi];
+    }
+    // vector offsets follow the caller's order so that batch vectors are laid
+    // out instance by instance as the caller listed them
+    {
+        std::vector<int64_t> off(count);
+        for (int i = 0; i < count; ++i) {
+            off[i] = voff;
+            voff += items[i].tables->dim;
+        }
+        for (int j = 0; j < count; ++j) inst[j].vec_off = off[sorted[j]];
+        for (int j = 0; j < count; ++j) {
+            const int64_t D = inst[j].dim;
+            for (int64_t s = 0; s < D; s += kChunk) {
+                BatchChunk c;
+                c.inst = j;
+                c.pad = 0;
+                c.start = inst[j].vec_off + s;
+                c.len = D - s < kChunk ? D - s : kChunk;
+                chunks.push_back(c);
+            }
+        }
+    }
+    b->total_len = voff;
+    b->nchunks = (int64_t)chunks.size();
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+    }
+    for (int gi = 0; gi < b->ngroups; ++gi) {
+        const int64_t need = (b->group_tiles[gi] + 3) / 4;
+        const int64_t cap_blocks = (int64_t)bpc * cus;
+        b->group_blocks[gi] = need < cap_blocks ? need : cap_blocks;
+        if (b->group_blocks[gi] < 1) b->group_blocks[gi] = 1;
+    }
+    b->inst_d = (BatchInst *)(base + L.inst);
+    b->tile_prefix_d = (int64_t *)(base + L.prefix);
+    b->chunks_d = (BatchChunk *)(base + L.chunks);
+    b->partials_d = (double2 *)(base + L.partials);
+    b->sorted_d = (int32_t *)(base + L.sorted);
+    b->pos_d = (int32_t *)(base + L.pos);
+    hipStream_t s = (hipStream_t)stream;
+    st = set_hip_error(hipMemcpyAsync(b->inst_d, inst.data(), sizeof(BatchInst) * count,
+                                      hipMemcpyHostToDevice, s));
+    if (!st) st = set_hip_error(hipMemcpyAsync(b->tile_prefix_d, prefix.data(),
+                                                sizeof(int64_t) * (count + 1),
+                                                hipMemcpyHostToDevice, s));
+    if (!st) st = set_hip_error(hipMemcpyAsync(b->chunks_d, chunks.data(),
+                                                sizeof(BatchChunk) * chunks.size(),
+                                                hipMemcpyHostToDevice, s));
+    if (!st) st = set_hip_error(hipMemcpyAsync(b->sorted_d, sorted.data(), sizeof(int32_t) * count,
+                                                hipMemcpyHostToDevice, s));
+    if (!st) st = set_hip_error(hipMemcpyAsync(b->pos_d, pos.data(), sizeof(int32_t) * count,
+                                                hipMemcpyHostToDevice, s));
+    // host staging vectors go out of scope: wait for the copies
+    if (!st) st = set_hip_error(hipStreamSynchronize(s));
+    if (st) {
+        free(b);
+        return st;
+    }
+    *out = b;
+    return MC_OK;
+}
+
+int mc_batch_destroy(mc_batch *b)
+{
+    free(b);
+    return MC_OK;
+}
+
+int64_t mc_batch_vector_length(const mc_batch *b) { return b ? b->total_len : (int64_t)MC_EINVAL; }
+
+int mc_batch_apply_H(const mc_batch *b, const double *C_d, double *HC_d, mc_stream stream)
+{
+    if (!b || !C_d || !HC_d) return MC_EINVAL;
+    if (overlaps(C_d, (size_t)b->total_len * 16, HC_d, (size_t)b->total_len * 16)) return MC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_batch_prep, dim3(4, b->count), dim3(256), 0, s, b->inst_d);
+    for (int gi = 0; gi < b->ngroups; ++gi) {
+        const int M = b->group_M[gi];
+        MC_DISPATCH_M(M, if constexpr (MT > 0) hipLaunchKernelGGL(
+                             (k_batch_apply<MT>), dim3(b->group_blocks[gi]), dim3(256), 0, s,
+                             b->inst_d, b->tile_prefix_d, b->group_first[gi], b->group_count[gi],
+                             b->group_tiles[gi], b->group_blocks[gi], b->order,
+                             (const double2 *)C_d, (double2 *)HC_d));
+    }
+    return launch_status();
+}
+
+int mc_batch_dot(const mc_batch *b, const double *x_d, const double *y_d, double *out_d,
+                 mc_stream stream)
+{
+    if (!b || !x_d || !y_d || !out_d) return MC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t grid = b->nchunks < 4096 ? b->nchunks : 4096;
+    hipLaunchKernelGGL(k_seg_dot_partial, dim3(grid), dim3(256), 0, s, b->chunks_d, b->nchunks,
+                       (const double2 *)x_d, (const double2 *)y_d, b->partials_d);
+    hipLaunchKernelGGL(k_seg_final, dim3((b->count + 255) / 256), dim3(256), 0, s, b->chunks_d,
+                       b->nchunks, b->count, b->sorted_d, b->partials_d, (double2 *)out_d,
+                       (double *)nullptr);
+    return launch_status();
+}
+
+int mc_batch_lanczos_orth(const mc_batch *b, double *w_d, const double *v_d,
+                          const double *vprev_d, const double *alpha_d, const double *beta_d,
+                          mc_stream stream)
+{
+    if (!b || !w_d || !v_d || !alpha_d) return MC_EINVAL;
+    const int64_t grid = b->nchunks < 8192 ? b->nchunks : 8192;
+    hipLaunchKernelGGL(k_seg_orth, dim3(grid), dim3(256), 0, (hipStream_t)stream, b->chunks_d,
+                       b->nchunks, b->sorted_d, (double2 *)w_d, (const double2 *)v_d,
+                       (const double2 *)vprev_d, (const double2 *)alpha_d, beta_d);
+    return launch_status();
+}
+
+int mc_batch_normalize(const mc_batch *b, const double *w_d, double *out_d, double *beta_d,
+                       mc_stream stream)
+{
+    if (!b || !w_d || !out_d || !beta_d) return MC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t grid = b->nchunks < 4096 ? b->nchunks : 4096;
+    hipLaunchKernelGGL(k_seg_dot_partial, dim3(grid), dim3(256), 0, s, b->chunks_d, b->nchunks,
+                       (const double2 *)w_d, (const double2 *)w_d, b->partials_d);
+    hipLaunchKernelGGL(k_seg_final, dim3((b->count + 255) / 256), dim3(256), 0, s, b->chunks_d,
+                       b->nchunks, b->count, b->sorted_d, b->partials_d, (double2 *)nullptr,
+                       beta_d);
+    const int64_t grid2 = b->nchunks < 8192 ? b->nchunks : 8192;
+    hipLaunchKernelGGL(k_seg_scale, dim3(grid2), dim3(256), 0, s, b->chunks_d, b->nchunks,
+                       b->sorted_d, (const double2 *)w_d, beta_d, (double2 *)out_d);
+    return launch_status();
+}
+
+}  // extern "C"

@@ -11,6 +11,7 @@
 // row validity; only the tile-uniform pair mask branches.
 #include <utility>
 
+#include "mc_apply.h"
 #include "mc_internal.h"
 
 namespace mc {
@@ -60,393 +61,22 @@ __global__ void k_prep(int M, int adjoint, const double2 *__restrict__ g,
     }
 }
 
-// Vectors of up to 2^28 entries go through a range-checked buffer resource
-// (any t outside [0, D) reads zero); larger ones (BIGC) use 64-bit addresses
-// with an explicit range test.
-template <bool BIGC>
-struct Gather {
-    __amdgpu_buffer_rsrc_t r;
-    const double2 *__restrict__ p;
-    int64_t n;
-    __device__ __forceinline__ Gather(const double2 *C, int64_t D)
-    {
-        p = C;
-        n = D;
-        if (!BIGC) r = make_rsrc(C, (uint32_t)(D * 16));
-    }
-    __device__ __forceinline__ double2 operator()(int32_t t) const
-    {
-        if (!BIGC) return buf_ld_c128(r, (uint32_t)t << 4);
-        const bool ok = t >= 0 && t < n;
-        const double2 v = p[ok ? t : 0];
-        return ok ? v : make_double2(0.0, 0.0);
-    }
-};
-
-// Per-row square roots of small integers used by the jump amplitudes.
-template <int MA>
-struct Roots {
-    double s0[MA], sm1[MA], sp1[MA], sp2[MA];
-};
-
-template <int MT, typename OccT>
-__device__ __forceinline__ void load_row(const OccT *__restrict__ occ, int64_t tile, int M,
-                                         int lane, int *n, Roots<(MT > 0 ? MT : MC_MAX_M)> &R)
-{
-    constexpr int MA = MT > 0 ? MT : MC_MAX_M;
-#pragma unroll (kUnroll<MT>)
-    for (int m = 0; m < MA; ++m) {
-        if (MT == 0 && m >= M) break;
-        n[m] = (int)occ[(tile * M + m) * kTile + lane];
-        const double x = (double)n[m];
-        R.s0[m] = sqrt(x);
-        R.sm1[m] = sqrt(x > 1.0 ? x - 1.0 : 0.0);
-        R.sp1[m] = sqrt(x + 1.0);
-        R.sp2[m] = sqrt(x + 2.0);
-    }
-}
-
-// Removal pair p (lexicographic k <= s) -> (k, s), for compile-time use.
-__host__ __device__ constexpr int pair_k(int M, int p)
-{
-    for (int k = 0; k < M; ++k) {
-        if (p < M - k) return k;
-        p -= M - k;
-    }
-    return -1;
-}
-__host__ __device__ constexpr int pair_s(int M, int p)
-{
-    for (int k = 0; k < M; ++k) {
-        if (p < M - k) return k + p;
-        p -= M - k;
-    }
-    return -1;
-}
-
-// Slots of one removal pair handled per batch: a batch issues all its table
-// loads, then all its gathers, then the arithmetic.
-#ifndef MC_SLOT_BATCH
-#define MC_SLOT_BATCH 13
-#endif
-template <int MT>
-constexpr int kSlotBatch = MT * MT < MC_SLOT_BATCH ? MT * MT : MC_SLOT_BATCH;
-
-// Contribution of removal pair P = (K, S), K <= S, to one row:
-//   A_KS * sum_{q,l} G'_{P,ql} B_ql(m) C[T2 slot],   m = n - e_K - e_S,
-// with `blk` this tile's block of M*M*64 entries for the pair.  Lanes whose
-// row cannot lose (K, S) hold -1 entries (gathers read 0) and get A = 0.
-template <int MT, bool BIGC, int P>
-__device__ __forceinline__ void pair_term(const int32_t *blk, int lane, const int (&n)[MT],
-                                          const Roots<MT> &R, const double2 *__restrict__ gp,
-                                          const Gather<BIGC> &ldc, double &ar, double &ai)
-{
-    constexpr int K = pair_k(MT, P), S = pair_s(MT, P);
-    constexpr int NS = MT * MT, SB = kSlotBatch<MT>;
-    const __amdgpu_buffer_rsrc_t r2 = make_rsrc(blk, (uint32_t)(NS * kTile * 4));
-    const bool valid = K == S ? n[K] >= 2 : (n[K] >= 1 && n[S] >= 1);
-    const double A = valid ? R.s0[K] * (K == S ? R.sm1[K] : R.s0[S]) : 0.0;
-    // creation amplitudes on m: rq = sqrt(m_q + 1), dq = sqrt(m_q + 2)
-    double rq[MT], dq[MT];
-#pragma unroll
-    for (int q = 0; q < MT; ++q) {
-        const int d = (q == K) + (q == S);
-        rq[q] = d == 0 ? R.sp1[q] : (d == 1 ? R.s0[q] : R.sm1[q]);
-        dq[q] = d == 0 ? R.sp2[q] : (d == 1 ? R.sp1[q] : R.s0[q]);
-    }
-    const double2 *G = gp + P * NS;
-    double br = 0.0, bi = 0.0;
-#pragma unroll
-    for (int j0 = 0; j0 < NS; j0 += SB) {
-        int32_t t[SB];
-        double2 c[SB];
-#pragma unroll
-        for (int i = 0; i < SB; ++i)
-            if (j0 + i < NS) t[i] = buf_ld_i32(r2, (uint32_t)(((j0 + i) * kTile + lane) * 4), 0);
-#pragma unroll
-        for (int i = 0; i < SB; ++i)
-            if (j0 + i < NS) c[i] = ldc(t[i]);
-#pragma unroll
-        for (int i = 0; i < SB; ++i) {
-            const int j = j0 + i;
-            if (j >= NS) break;
-            const int q = j / MT, l = j % MT;
-            const double B = q == l ? rq[q] * dq[q] : rq[q] * rq[l];
-            const double cr = c[i].x * B, ci = c[i].y * B;
-            const double2 Gv = G[j];
-            br = fma(Gv.x, cr, br);
-            br = fma(-Gv.y, ci, br);
-            bi = fma(Gv.x, ci, bi);
-            bi = fma(Gv.y, cr, bi);
-        }
-    }
-    ar = fma(A, br, ar);
-    ai = fma(A, bi, ai);
-}
-
-// All removal pairs in order; each present pair is its own basic block
-// (uniform branch on the tile's pair mask), which keeps the scheduler from
-// hoisting later pairs' loads.
-template <int MT, bool BIGC, int... Ps>
-__device__ __forceinline__ void all_pairs(std::integer_sequence<int, Ps...>,
-                                          const uint64_t *pm, const int32_t *t2, int64_t off0,
-                                          int64_t off1, int lane, const int (&n)[MT],
-                                          const Roots<MT> &R, const double2 *__restrict__ gp,
-                                          const Gather<BIGC> &ldc, double &ar, double &ai)
-{
-    int64_t pos = off0;
-    (
-        [&] {
-            constexpr int NSB = MT * MT * kTile;
-            if (((pm[Ps >> 6] >> (Ps & 63)) & 1) && pos + NSB <= off1) {
-                pair_term<MT, BIGC, Ps>(t2 + pos, lane, n, R, gp, ldc, ar, ai);
-                pos += NSB;
-            }
-        }(),
-        ...);
-}
-
-// H.C for a compile-time orbital count MT (1..8); every orbital, pair and
-// slot index is a compile-time constant.
 template <int MT, typename OccT, bool BIGC>
-__global__ __launch_bounds__(256) void k_apply(int64_t D, int64_t tiles, int64_t nblocks,
-                                                int64_t cap, const OccT *__restrict__ occ,
-                                                const int32_t *__restrict__ t1,
-                                                const uint64_t *__restrict__ pmask,
-                                                const int64_t *__restrict__ t2_off,
-                                                const int32_t *__restrict__ t2,
-                                                const double2 *__restrict__ h,
-                                                const double2 *__restrict__ gp,
-                                                const double2 *__restrict__ C,
-                                                double2 *__restrict__ HC)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MC_APPLY_WAVES)))
+void k_apply(int64_t D, int64_t tiles, int64_t nblocks, int64_t cap, const OccT *__restrict__ occ,
+             const int32_t *__restrict__ t1, const uint64_t *__restrict__ pmask,
+             const int64_t *__restrict__ t2_off, const int32_t *__restrict__ t2,
+             const double2 *__restrict__ h, const double2 *__restrict__ gp,
+             const double2 *__restrict__ C, double2 *__restrict__ HC)
 {
-    constexpr int M = MT;
-    constexpr int P = M * (M + 1) / 2;
-    constexpr int W = (P + 63) / 64;
-    const int lane = threadIdx.x & 63;
     const int64_t tile = xcd_block(blockIdx.x, nblocks) * 4 + wave_in_block();
     if (tile >= tiles) return;
-    const int64_t g = tile * kTile + lane;
-    const bool live = g < D;
-
-    int n[M];
-    Roots<M> R;
-    load_row<MT, OccT>(occ, tile, M, lane, n, R);
-    const Gather<BIGC> ldc(C, D);
-
-    // diagonal one-body part: sum_k h_kk n_k C_g
-    const double2 cg = ldc(live ? (int32_t)g : -1);
-    double ar, ai;
-    {
-        double dr = 0.0, di = 0.0;
-#pragma unroll
-        for (int k = 0; k < M; ++k) {
-            const double2 hk = h[k * M + k];
-            dr = fma(hk.x, (double)n[k], dr);
-            di = fma(hk.y, (double)n[k], di);
-        }
-        ar = dr * cg.x - di * cg.y;
-        ai = dr * cg.y + di * cg.x;
-    }
-
-    // single jumps k -> l (k != l): h_kl sqrt(n_k (n_l + 1)) C[T1]
-    {
-        constexpr int S1 = M * (M - 1);
-        const __amdgpu_buffer_rsrc_t r1 =
-            make_rsrc(t1 + tile * M * M * kTile, (uint32_t)(M * M * kTile * 4));
-        int32_t t[S1 > 0 ? S1 : 1];
-        int j = 0;
-#pragma unroll
-        for (int k = 0; k < M; ++k)
-#pragma unroll
-            for (int l = 0; l < M; ++l)
-                if (l != k) t[j++] = buf_ld_i32(r1, (uint32_t)(((k * M + l) * kTile + lane) * 4), 0);
-        double2 c[S1 > 0 ? S1 : 1];
-#pragma unroll
-        for (int i = 0; i < S1; ++i) c[i] = ldc(t[i]);
-        j = 0;
-#pragma unroll
-        for (int k = 0; k < M; ++k)
-#pragma unroll
-            for (int l = 0; l < M; ++l) {
-                if (l == k) continue;
-                const double f = R.s0[k] * R.sp1[l];
-                const double2 hv = h[k * M + l];
-                const double cr = c[j].x * f, ci = c[j].y * f;
-                ++j;
-                ar = fma(hv.x, cr, ar);
-                ar = fma(-hv.y, ci, ar);
-                ai = fma(hv.x, ci, ai);
-                ai = fma(hv.y, cr, ai);
-            }
-    }
-
-    // double jumps: one block of M*M*64 entries per pair present in the tile
-    {
-        int64_t off0, off1;
-        t2_block(t2_off, tile, cap, off0, off1);
-        all_pairs<MT, BIGC>(std::make_integer_sequence<int, P>{}, pmask + tile * W, t2, off0, off1,
-                            lane, n, R, gp, ldc, ar, ai);
-    }
-    if (live) HC[g] = make_double2(ar, ai);
-}
-
-// ---------------------------------------------------------------------------
-// H.C without the double-jump map: a double jump (k, s) -> (q, l) is two
-// single jumps, first k -> q from the row, then s -> l from that
-// intermediate configuration,
-//     T2[g][(k,s)][q*M + l] = T1[T1[g][k][q]][s][l],
-// which holds for every valid removal pair (the intermediate still has a
-// particle in s).  The tile's single-jump rows stay in registers (they also
-// feed the one-body term); the second hop is a gather from rows near g.
-// ---------------------------------------------------------------------------
-template <int MT, bool BIGC, int P>
-__device__ __forceinline__ void pair_term_chained(int64_t D, const int32_t *__restrict__ t1,
-                                                  int lane, const int (&n)[MT],
-                                                  const Roots<MT> &R,
-                                                  const int32_t (&tr)[MT * MT],
-                                                  const double2 *__restrict__ gp,
-                                                  const Gather<BIGC> &ldc, double &ar,
-                                                  double &ai)
-{
-    constexpr int K = pair_k(MT, P), S = pair_s(MT, P);
-    constexpr int NS = MT * MT, SB = kSlotBatch<MT>;
-    const bool valid = K == S ? n[K] >= 2 : (n[K] >= 1 && n[S] >= 1);
-    if (!__ballot(valid)) return;   // no row of the tile can lose (K, S)
-    const double A = valid ? R.s0[K] * (K == S ? R.sm1[K] : R.s0[S]) : 0.0;
-    double rq[MT], dq[MT];
-#pragma unroll
-    for (int q = 0; q < MT; ++q) {
-        const int d = (q == K) + (q == S);
-        rq[q] = d == 0 ? R.sp1[q] : (d == 1 ? R.s0[q] : R.sm1[q]);
-        dq[q] = d == 0 ? R.sp2[q] : (d == 1 ? R.sp1[q] : R.s0[q]);
-    }
-    const double2 *G = gp + P * NS;
-    double br = 0.0, bi = 0.0;
-#pragma unroll
-    for (int j0 = 0; j0 < NS; j0 += SB) {
-        int32_t t[SB];
-        double2 c[SB];
-#pragma unroll
-        for (int i = 0; i < SB; ++i) {
-            const int j = j0 + i;
-            if (j >= NS) break;
-            const int q = j / MT, l = j % MT;
-            if (q == K) {
-                // first hop k -> k leaves the row unchanged
-                t[i] = valid ? tr[S * MT + l] : -1;
-            } else {
-                const int32_t b = tr[K * MT + q];
-                const bool ok = valid && b >= 0 && b < D;
-                const int64_t bb = ok ? b : 0;
-                const int32_t v = t1[((bb >> 6) * NS + S * MT + l) * kTile + (bb & 63)];
-                t[i] = ok ? v : -1;
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < SB; ++i)
-            if (j0 + i < NS) c[i] = ldc(t[i]);
-#pragma unroll
-        for (int i = 0; i < SB; ++i) {
-            const int j = j0 + i;
-            if (j >= NS) break;
-            const int q = j / MT, l = j % MT;
-            const double B = q == l ? rq[q] * dq[q] : rq[q] * rq[l];
-            const double cr = c[i].x * B, ci = c[i].y * B;
-            const double2 Gv = G[j];
-            br = fma(Gv.x, cr, br);
-            br = fma(-Gv.y, ci, br);
-            bi = fma(Gv.x, ci, bi);
-            bi = fma(Gv.y, cr, bi);
-        }
-    }
-    ar = fma(A, br, ar);
-    ai = fma(A, bi, ai);
-}
-
-template <int MT, bool BIGC, int... Ps>
-__device__ __forceinline__ void all_pairs_chained(std::integer_sequence<int, Ps...>, int64_t D,
-                                                  const int32_t *__restrict__ t1, int lane,
-                                                  const int (&n)[MT], const Roots<MT> &R,
-                                                  const int32_t (&tr)[MT * MT],
-                                                  const double2 *__restrict__ gp,
-                                                  const Gather<BIGC> &ldc, double &ar,
-                                                  double &ai)
-{
-    (pair_term_chained<MT, BIGC, Ps>(D, t1, lane, n, R, tr, gp, ldc, ar, ai), ...);
-}
-
-// One 64-row tile of H.C through single jumps only (see above).
-template <int MT, typename OccT, bool BIGC>
-__device__ __forceinline__ void apply_tile_chained(int64_t tile, int64_t D,
-                                                   const OccT *__restrict__ occ,
-                                                   const int32_t *__restrict__ t1,
-                                                   const double2 *__restrict__ h,
-                                                   const double2 *__restrict__ gp,
-                                                   const double2 *__restrict__ C,
-                                                   double2 *__restrict__ HC)
-{
-    constexpr int M = MT;
-    constexpr int P = M * (M + 1) / 2;
-    const int lane = threadIdx.x & 63;
-    const int64_t g = tile * kTile + lane;
-    const bool live = g < D;
-    int n[M];
-    Roots<M> R;
-    load_row<MT, OccT>(occ, tile, M, lane, n, R);
-    const Gather<BIGC> ldc(C, D);
-    int32_t tr[M * M];
-    {
-        const __amdgpu_buffer_rsrc_t r1 =
-            make_rsrc(t1 + tile * M * M * kTile, (uint32_t)(M * M * kTile * 4));
-#pragma unroll
-        for (int j = 0; j < M * M; ++j) tr[j] = buf_ld_i32(r1, (uint32_t)((j * kTile + lane) * 4), 0);
-    }
-    const double2 cg = ldc(live ? (int32_t)g : -1);
-    double ar, ai;
-    {
-        double dr = 0.0, di = 0.0;
-#pragma unroll
-        for (int k = 0; k < M; ++k) {
-            const double2 hk = h[k * M + k];
-            dr = fma(hk.x, (double)n[k], dr);
-            di = fma(hk.y, (double)n[k], di);
-        }
-        ar = dr * cg.x - di * cg.y;
-        ai = dr * cg.y + di * cg.x;
-    }
-    {
-        constexpr int S1 = M * (M - 1);
-        double2 c[S1 > 0 ? S1 : 1];
-        int j = 0;
-#pragma unroll
-        for (int k = 0; k < M; ++k)
-#pragma unroll
-            for (int l = 0; l < M; ++l)
-                if (l != k) c[j++] = ldc(tr[k * M + l]);
-        j = 0;
-#pragma unroll
-        for (int k = 0; k < M; ++k)
-#pragma unroll
-            for (int l = 0; l < M; ++l) {
-                if (l == k) continue;
-                const double f = R.s0[k] * R.sp1[l];
-                const double2 hv = h[k * M + l];
-                const double cr = c[j].x * f, ci = c[j].y * f;
-                ++j;
-                ar = fma(hv.x, cr, ar);
-                ar = fma(-hv.y, ci, ar);
-                ai = fma(hv.x, ci, ai);
-                ai = fma(hv.y, cr, ai);
-            }
-    }
-    all_pairs_chained<MT, BIGC>(std::make_integer_sequence<int, P>{}, D, t1, lane, n, R, tr, gp,
-                                ldc, ar, ai);
-    if (live) HC[g] = make_double2(ar, ai);
+    apply_tile_t2<MT, OccT, BIGC>(tile, D, cap, occ, t1, pmask, t2_off, t2, h, gp, C, HC);
 }
 
 template <int MT, typename OccT, bool BIGC>
-__global__ __launch_bounds__(256) void k_apply_chained(int64_t D, int64_t tiles, int64_t nblocks,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MC_APPLY_WAVES)))
+void k_apply_chained(int64_t D, int64_t tiles, int64_t nblocks,
                                                         const OccT *__restrict__ occ,
                                                         const int32_t *__restrict__ t1,
                                                         const double2 *__restrict__ h,

@@ -99,3 +99,27 @@ def test_large_space_sampled_rows(mc, oracle_native):
     assert abs(e.imag) <= 1e-12 * abs(e.real)
     del tab, hc, Cd
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("N,M,seed", [(1, 3, 0), (2, 2, 1), (3, 5, 4), (10, 5, 0), (7, 4, 5), (5, 7, 6),
+                                      (6, 8, 7), (300, 2, 12), (40, 4, 14)])
+def test_apply_chained_single_jumps_matches_oracle(mc, oracle_native, N, M, seed):
+    """Without the double-jump map the apply chains two single jumps."""
+    C, h, g = W.random_instance(N, M, seed)
+    tab = mc.build_tables(N, M, double_jumps=False)
+    assert tab.t2 is None
+    hc = mc.apply_H(dev(h), dev(g), dev(C), tab).cpu().numpy()
+    assert rel_inf(hc, oracle_native.apply_h(N, M, h, g, C)) <= TOL
+
+
+def test_apply_chained_large_space_sampled_rows(mc, oracle_native):
+    N, M = 200, 5
+    C, h, g = W.random_instance(N, M, 2)
+    tab = mc.build_tables(N, M, double_jumps=False)
+    hc = mc.apply_H(dev(h), dev(g), dev(C), tab)
+    rng = np.random.default_rng(3)
+    rows = np.unique(np.concatenate([rng.integers(0, C.size, 1000), np.arange(64), C.size - 1 - np.arange(64)]))
+    got = hc[torch.from_numpy(rows).cuda()].cpu().numpy()
+    assert rel_inf(got, oracle_native.apply_h(N, M, h, g, C, rows)) <= TOL
+    del tab, hc
+    torch.cuda.empty_cache()
