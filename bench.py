@@ -99,6 +99,103 @@ def cpu_baseline(N, M, h, g, C, budget_s: float = 15.0) -> dict:
     }
 
 
+def _median_ms(fn, reps, stream):
+    import torch
+    times = []
+    for _ in range(reps):
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record(stream)
+        fn()
+        e.record(stream)
+        torch.cuda.synchronize()
+        times.append(s.elapsed_time(e))
+    times.sort()
+    return times[len(times) // 2]
+
+
+def autograd_leg(dev) -> dict:
+    """E = <C|H C> forward + backward (dC, dh, dg) vs one plain apply, N=50, M=6."""
+    import torch
+    import paper_2005_13679_amd as mc
+    import workloads as W
+    N, M = 50, 6
+    C, h, g = W.random_instance(N, M, 3)
+    tab = mc.build_tables(N, M, dev)
+    Cd, hd, gd = (torch.from_numpy(x).to(dev) for x in (C, h, g))
+    HC = torch.empty_like(Cd)
+    stream = torch.cuda.current_stream(dev)
+    mc.apply_H(hd, gd, Cd, tab, out=HC)
+    plain = _median_ms(lambda: mc.apply_H(hd, gd, Cd, tab, out=HC), 10, stream)
+    Cg, hg, gg = (x.clone().requires_grad_(True) for x in (Cd, hd, gd))
+
+    def fwd_bwd():
+        for x in (Cg, hg, gg):
+            x.grad = None
+        mc.energy(Cg, hg, gg, tab).real.backward()
+
+    fwd_bwd()
+    full = _median_ms(fwd_bwd, 5, stream)
+    rho2 = _median_ms(lambda: mc.rho2(Cd, tab), 5, stream)
+    rho1 = _median_ms(lambda: mc.rho1(Cd, tab), 5, stream)
+    del tab
+    torch.cuda.empty_cache()
+    return {"workload": f"N={N}, M={M}, dim {C.size}", "plain_apply_ms": plain,
+            "energy_fwd_bwd_ms": full, "ratio_fwd_bwd_over_apply": full / plain,
+            "rho1_ms": rho1, "rho2_ms": rho2}
+
+
+def batched_leg(dev, steps: int = 50) -> dict:
+    """64 seeded instances (N ~ U{8..40}, M ~ U{3..8}): 50 Lanczos steps for all
+    of them in one captured graph (autotuned schedule) vs the same steps per
+    instance with the single-instance calls."""
+    import torch
+    import paper_2005_13679_amd as mc
+    from paper_2005_13679_amd import autotune
+    from paper_2005_13679_amd.batch import Batch, BatchedLanczos, choose_double_jumps, plain_lanczos
+    import workloads as W
+    draws = W.batch_draws(64, 4)
+    use_t2 = choose_double_jumps(draws, budget_bytes=40e9)
+    insts = []
+    for i, ((N, M), t2) in enumerate(zip(draws, use_t2)):
+        _, h, g = W.random_instance(1, M, 1000 + i)
+        tab = mc.build_tables(N, M, dev, double_jumps=t2)
+        insts.append((tab, torch.from_numpy(h).to(dev), torch.from_numpy(g).to(dev)))
+    total_dim = sum(t.dim for t, _, _ in insts)
+    tuned = autotune.tune(insts, cache_path=os.path.join(ROOT, "gpurun_out", "autotune_cache.json"),
+                          reps=2)
+    b = Batch(insts, tuned["schedule"])
+    rng = np.random.default_rng(9)
+    v0 = b.vector()
+    for i, (t, _, _) in enumerate(insts):
+        b.segment(v0, i).copy_(torch.from_numpy(W.random_coefficients(rng, t.dim)).to(dev))
+    lz = BatchedLanczos(b, steps, graph=True)
+    a_b, be_b = lz.run(v0)                       # warm replay
+    t0 = time.perf_counter()
+    a_b, be_b = lz.run(v0)
+    t_batch = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    worst = 0.0
+    for i, (t, hd, gd) in enumerate(insts):
+        a_p, b_p = plain_lanczos(t, hd, gd, b.segment(v0, i).contiguous(), steps)
+        torch.cuda.synchronize()
+        k = min(steps, t.dim - 1, 8)
+        a_p = a_p.real.cpu().numpy()
+        if k > 0:
+            worst = max(worst, float(np.max(np.abs(a_p[:k] - a_b[:k, i]) / np.maximum(1.0, np.abs(a_p[:k])))))
+    t_plain = time.perf_counter() - t0
+    out = {"instances": len(insts), "total_dim": int(total_dim),
+           "with_double_jump_map": int(sum(use_t2)), "steps": steps,
+           "schedule": tuned["schedule"], "schedule_cached": tuned["cached"],
+           "batched_graph_s": t_batch, "plain_eager_s": t_plain,
+           "batched_instance_applies_per_s": len(insts) * steps / t_batch,
+           "plain_instance_applies_per_s": len(insts) * steps / t_plain,
+           "speedup": t_plain / t_batch, "max_rel_alpha_diff_first_steps": worst}
+    del lz, b, insts
+    torch.cuda.empty_cache()
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +204,8 @@ def main(argv=None):
     ap.add_argument("--workload", default="large_random", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--extras", action="store_true", help="also time rho1/rho2 passes")
+    ap.add_argument("--quick", action="store_true",
+                    help="skip the autograd and batched comparison legs")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="run one elementwise copy of this size first (HBM counter scale)")
     args = ap.parse_args(argv)
@@ -203,6 +302,14 @@ def main(argv=None):
             torch.cuda.synchronize()
             extras[f"{name}_ms"] = s.elapsed_time(e)
         out["extras"] = extras
+
+    if not args.quick:
+        del tab
+        torch.cuda.empty_cache()
+        print("[bench] autograd leg (N=50, M=6)", file=sys.stderr, flush=True)
+        out["autograd_vs_plain"] = autograd_leg(dev)
+        print("[bench] batched leg (64 instances, 50 Lanczos steps)", file=sys.stderr, flush=True)
+        out["batched_vs_plain"] = batched_leg(dev)
 
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a row sample", file=sys.stderr, flush=True)

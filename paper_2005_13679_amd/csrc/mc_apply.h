@@ -87,18 +87,83 @@ __host__ __device__ constexpr int pair_s(int M, int p)
 template <int MT>
 constexpr int kSlotBatch = MT * MT < MC_SLOT_BATCH ? MT * MT : MC_SLOT_BATCH;
 
+// Indices of slots [J0, J0 + SB) of a double-jump block (one per lane).
+template <int MT, int SB, int J0>
+__device__ __forceinline__ void load_t2_batch(int32_t (&t)[SB], __amdgpu_buffer_rsrc_t r, int lane)
+{
+    constexpr int NS = MT * MT;
+#pragma unroll
+    for (int i = 0; i < SB; ++i)
+        if (J0 + i < NS) t[i] = buf_ld_i32(r, (uint32_t)(((J0 + i) * kTile + lane) * 4), 0);
+}
+
+// Resource over the double-jump block starting at `pos`, clipped to the
+// tile's [., off1) range (a zero-length resource makes loads return 0).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t t2_block_rsrc(const int32_t *t2, int64_t pos,
+                                                                int64_t off1, int ns)
+{
+    int64_t n = off1 - pos;
+    n = n < 0 ? 0 : (n > (int64_t)ns * kTile ? (int64_t)ns * kTile : n);
+    return make_rsrc(t2 + (pos < off1 ? pos : off1), (uint32_t)(n * 4));
+}
+
 // Contribution of removal pair P = (K, S), K <= S, to one row:
 //   A_KS * sum_{q,l} G'_{P,ql} B_ql(m) C[T2 slot],   m = n - e_K - e_S,
-// with `blk` this tile's block of M*M*64 entries for the pair.  Lanes whose
-// row cannot lose (K, S) hold -1 entries (gathers read 0) and get A = 0.
+// for the pair's block at `pos` (M*M*64 entries).  Lanes whose row cannot
+// lose (K, S) hold -1 entries (gathers read 0) and get A = 0.
+// Software pipeline: `tf` holds the first index batch of this block on entry
+// (loaded earlier); batch b's gathers are issued, then the next batch's
+// indices are loaded (after the last batch: the first batch of the next
+// block, which is simply the next M*M*64 entries since the blocks of the
+// present pairs are contiguous), then batch b's arithmetic waits for its
+// gathers.
+template <int MT, bool BIGC, int B, int NB>
+__device__ __forceinline__ void pair_batches(const int32_t *t2, int64_t pos, int64_t off1, int lane,
+                                             __amdgpu_buffer_rsrc_t r2,
+                                             int32_t (&tf)[kSlotBatch<MT>],
+                                             int32_t (&tn)[kSlotBatch<MT>], const double (&rq)[MT],
+                                             const double (&dq)[MT], const double2 *__restrict__ G,
+                                             const Gather<BIGC> &ldc, double &br, double &bi)
+{
+    if constexpr (B < NB) {
+        constexpr int NS = MT * MT, SB = kSlotBatch<MT>, J0 = B * SB;
+        double2 c[SB];
+#pragma unroll
+        for (int i = 0; i < SB; ++i)
+            if (J0 + i < NS) c[i] = ldc(B == 0 ? tf[i] : tn[i]);
+        if constexpr (B + 1 < NB) {
+            load_t2_batch<MT, SB, J0 + SB>(tn, r2, lane);
+        } else {
+            const __amdgpu_buffer_rsrc_t rn = t2_block_rsrc(t2, pos + NS * kTile, off1, NS);
+            load_t2_batch<MT, SB, 0>(tf, rn, lane);
+        }
+#pragma unroll
+        for (int i = 0; i < SB; ++i) {
+            const int j = J0 + i;
+            if (j >= NS) break;
+            const int q = j / MT, l = j % MT;
+            const double Bf = q == l ? rq[q] * dq[q] : rq[q] * rq[l];
+            const double cr = c[i].x * Bf, ci = c[i].y * Bf;
+            const double2 Gv = G[j];
+            br = fma(Gv.x, cr, br);
+            br = fma(-Gv.y, ci, br);
+            bi = fma(Gv.x, ci, bi);
+            bi = fma(Gv.y, cr, bi);
+        }
+        pair_batches<MT, BIGC, B + 1, NB>(t2, pos, off1, lane, r2, tf, tn, rq, dq, G, ldc, br, bi);
+    }
+}
+
 template <int MT, bool BIGC, int P>
-__device__ __forceinline__ void pair_term(const int32_t *blk, int lane, const int (&n)[MT],
-                                          const Roots<MT> &R, const double2 *__restrict__ gp,
-                                          const Gather<BIGC> &ldc, double &ar, double &ai)
+__device__ __forceinline__ void pair_term(const int32_t *t2, int64_t pos, int64_t off1, int lane,
+                                          const int (&n)[MT], const Roots<MT> &R,
+                                          const double2 *__restrict__ gp, const Gather<BIGC> &ldc,
+                                          int32_t (&tf)[kSlotBatch<MT>], double &ar, double &ai)
 {
     constexpr int K = pair_k(MT, P), S = pair_s(MT, P);
     constexpr int NS = MT * MT, SB = kSlotBatch<MT>;
-    const __amdgpu_buffer_rsrc_t r2 = make_rsrc(blk, (uint32_t)(NS * kTile * 4));
+    constexpr int NB = (NS + SB - 1) / SB;
+    const __amdgpu_buffer_rsrc_t r2 = make_rsrc(t2 + pos, (uint32_t)(NS * kTile * 4));
     const bool valid = K == S ? n[K] >= 2 : (n[K] >= 1 && n[S] >= 1);
     const double A = valid ? R.s0[K] * (K == S ? R.sm1[K] : R.s0[S]) : 0.0;
     // creation amplitudes on m: rq = sqrt(m_q + 1), dq = sqrt(m_q + 2)
@@ -109,52 +174,31 @@ __device__ __forceinline__ void pair_term(const int32_t *blk, int lane, const in
         rq[q] = d == 0 ? R.sp1[q] : (d == 1 ? R.s0[q] : R.sm1[q]);
         dq[q] = d == 0 ? R.sp2[q] : (d == 1 ? R.sp1[q] : R.s0[q]);
     }
-    const double2 *G = gp + P * NS;
+    int32_t tn[SB];
     double br = 0.0, bi = 0.0;
-#pragma unroll
-    for (int j0 = 0; j0 < NS; j0 += SB) {
-        int32_t t[SB];
-        double2 c[SB];
-#pragma unroll
-        for (int i = 0; i < SB; ++i)
-            if (j0 + i < NS) t[i] = buf_ld_i32(r2, (uint32_t)(((j0 + i) * kTile + lane) * 4), 0);
-#pragma unroll
-        for (int i = 0; i < SB; ++i)
-            if (j0 + i < NS) c[i] = ldc(t[i]);
-#pragma unroll
-        for (int i = 0; i < SB; ++i) {
-            const int j = j0 + i;
-            if (j >= NS) break;
-            const int q = j / MT, l = j % MT;
-            const double B = q == l ? rq[q] * dq[q] : rq[q] * rq[l];
-            const double cr = c[i].x * B, ci = c[i].y * B;
-            const double2 Gv = G[j];
-            br = fma(Gv.x, cr, br);
-            br = fma(-Gv.y, ci, br);
-            bi = fma(Gv.x, ci, bi);
-            bi = fma(Gv.y, cr, bi);
-        }
-    }
+    pair_batches<MT, BIGC, 0, NB>(t2, pos, off1, lane, r2, tf, tn, rq, dq, gp + P * NS, ldc, br, bi);
     ar = fma(A, br, ar);
     ai = fma(A, bi, ai);
 }
 
 // All removal pairs in order; each present pair is its own basic block
 // (uniform branch on the tile's pair mask), which keeps the scheduler from
-// hoisting later pairs' loads.
+// hoisting later pairs' loads.  `tf` carries the prefetched first index
+// batch of the next block from pair to pair.
 template <int MT, bool BIGC, int... Ps>
 __device__ __forceinline__ void all_pairs(std::integer_sequence<int, Ps...>,
                                           const uint64_t *pm, const int32_t *t2, int64_t off0,
                                           int64_t off1, int lane, const int (&n)[MT],
                                           const Roots<MT> &R, const double2 *__restrict__ gp,
-                                          const Gather<BIGC> &ldc, double &ar, double &ai)
+                                          const Gather<BIGC> &ldc, int32_t (&tf)[kSlotBatch<MT>],
+                                          double &ar, double &ai)
 {
     int64_t pos = off0;
     (
         [&] {
             constexpr int NSB = MT * MT * kTile;
             if (((pm[Ps >> 6] >> (Ps & 63)) & 1) && pos + NSB <= off1) {
-                pair_term<MT, BIGC, Ps>(t2 + pos, lane, n, R, gp, ldc, ar, ai);
+                pair_term<MT, BIGC, Ps>(t2, pos, off1, lane, n, R, gp, ldc, tf, ar, ai);
                 pos += NSB;
             }
         }(),
@@ -182,6 +226,13 @@ __device__ __forceinline__ void apply_tile_t2(int64_t tile, int64_t D, int64_t c
     const int lane = threadIdx.x & 63;
     const int64_t g = tile * kTile + lane;
     const bool live = g < D;
+
+    // first index batch of the tile's first double-jump block, in flight
+    // during the one-body part
+    int64_t off0, off1;
+    t2_block(t2_off, tile, cap, off0, off1);
+    int32_t tf[kSlotBatch<MT>];
+    load_t2_batch<MT, kSlotBatch<MT>, 0>(tf, t2_block_rsrc(t2, off0, off1, M * M), lane);
 
     int n[M];
     Roots<M> R;
@@ -242,12 +293,8 @@ __device__ __forceinline__ void apply_tile_t2(int64_t tile, int64_t D, int64_t c
     }
 
     // double jumps: one block of M*M*64 entries per pair present in the tile
-    {
-        int64_t off0, off1;
-        t2_block(t2_off, tile, cap, off0, off1);
-        all_pairs<MT, BIGC>(std::make_integer_sequence<int, P>{}, pmask + tile * W, t2, off0, off1,
-                            lane, n, R, gp, ldc, ar, ai);
-    }
+    all_pairs<MT, BIGC>(std::make_integer_sequence<int, P>{}, pmask + tile * W, t2, off0, off1,
+                        lane, n, R, gp, ldc, tf, ar, ai);
     if (live) HC[g] = make_double2(ar, ai);
 }
 

@@ -190,7 +190,7 @@ constexpr int kRhoWaves = 4096;
 inline int rho_waves(int64_t tiles) { return (int)(tiles < kRhoWaves ? tiles : kRhoWaves); }
 
 template <int MT, typename OccT, bool BIGC>
-__global__ __launch_bounds__(256) void k_rho1(int Mrt, int64_t D, int64_t tiles, int nwaves,
+__global__ __launch_bounds__(256) void k_rho1_generic(int Mrt, int64_t D, int64_t tiles, int nwaves,
                                                const OccT *__restrict__ occ,
                                                const int32_t *__restrict__ t1,
                                                const double2 *__restrict__ C,
@@ -251,86 +251,219 @@ __global__ __launch_bounds__(256) void k_rho1(int Mrt, int64_t D, int64_t tiles,
     }
 }
 
-// One wavefront per block.  Dynamic LDS holds, per lane, the occupations and
-// the four root tables of its row ([5][M][64] doubles, private to each lane
-// so no barrier is needed) followed by the wave's accumulator of
-// E = M(M+1)/2 * M^2 complex elements, updated by lane 0 only.
-template <typename OccT, bool BIGC>
-__global__ __launch_bounds__(64) void k_rho2(int M, int64_t D, int64_t tiles, int nwaves,
-                                              int64_t cap,
-                                              const OccT *__restrict__ occ,
-                                              const uint64_t *__restrict__ pmask,
-                                              const int64_t *__restrict__ t2_off,
-                                              const int32_t *__restrict__ t2,
-                                              const double2 *__restrict__ C,
-                                              double2 *__restrict__ part)
+// ---------------------------------------------------------------------------
+// Density matrices for M <= 8.  Each wavefront keeps per-lane partial sums
+// over all of its tiles (tiles w, w + nwaves, ...) and reduces across lanes
+// once at the end, so the cross-lane work does not grow with the number of
+// rows.  Square roots of small integers come from an LDS table.
+// ---------------------------------------------------------------------------
+constexpr int kRhoChunk = 32;   // slots accumulated per pass
+
+// sqrt(i) for i = 0 .. N+2 into LDS (block-wide)
+__device__ __forceinline__ void fill_sqrt_table(double *tab, int n)
 {
-    extern __shared__ double sh[];
-    const int E = M * (M + 1) / 2 * M * M;
-    double *roots = sh;                              // [5][M][64]
-    double2 *acc = (double2 *)(sh + 5 * M * kTile);  // [E]
-    const int lane = threadIdx.x;
-    const int wave = blockIdx.x;
-    if (wave >= nwaves) return;
-    for (int e = lane; e < E; e += kTile) acc[e] = make_double2(0.0, 0.0);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) tab[i] = sqrt((double)i);
     __syncthreads();
-    const Gather<BIGC> ldc(C, D);
-    const int W = (M * (M + 1) / 2 + 63) / 64;
-    auto root = [&](int which, int m) -> double { return roots[(which * M + m) * kTile + lane]; };
+}
+
+// rho1: elements e = k*M + l, chunk [J0, J0 + CH) of them per pass
+template <int MT, typename OccT, bool BIGC, int J0>
+__device__ __forceinline__ void rho1_chunk(int64_t D, int64_t tiles, int nwaves, int wave,
+                                           const OccT *__restrict__ occ,
+                                           const int32_t *__restrict__ t1,
+                                           const Gather<BIGC> &ldc, const double *sq,
+                                           double2 *__restrict__ part)
+{
+    constexpr int NS = MT * MT;
+    constexpr int CH = NS - J0 < kRhoChunk ? NS - J0 : kRhoChunk;
+    const int lane = threadIdx.x & 63;
+    double ar[CH], ai[CH];
+#pragma unroll
+    for (int i = 0; i < CH; ++i) ar[i] = ai[i] = 0.0;
     for (int64_t tile = wave; tile < tiles; tile += nwaves) {
         const int64_t g = tile * kTile + lane;
-        for (int m = 0; m < M; ++m) {
-            const double x = (double)occ[(tile * M + m) * kTile + lane];
-            roots[(0 * M + m) * kTile + lane] = sqrt(x > 1.0 ? x - 1.0 : 0.0);  // sqrt(n-1)
-            roots[(1 * M + m) * kTile + lane] = sqrt(x);                        // sqrt(n)
-            roots[(2 * M + m) * kTile + lane] = sqrt(x + 1.0);                  // sqrt(n+1)
-            roots[(3 * M + m) * kTile + lane] = sqrt(x + 2.0);                  // sqrt(n+2)
-            roots[(4 * M + m) * kTile + lane] = x;                              // n
-        }
+        int n[MT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) n[m] = (int)occ[(tile * MT + m) * kTile + lane];
         const double2 cg = ldc(g < D ? (int32_t)g : -1);
-        int64_t off0, off1;
-        t2_block(t2_off, tile, cap, off0, off1);
-        const __amdgpu_buffer_rsrc_t r2 = make_rsrc(t2 + off0, (uint32_t)((off1 - off0) * 4));
-        const uint64_t *pm = pmask + tile * W;
-        int rank = 0;
-        int p = 0;
-        for (int k = 0; k < M; ++k) {
-            for (int s = k; s < M; ++s, ++p) {
-                const uint64_t word = pm[p >> 6];
-                if (!((word >> (p & 63)) & 1)) continue;
-                const double xk = root(4, k), xs = root(4, s);
-                const bool valid = k == s ? xk >= 2.0 : (xk >= 1.0 && xs >= 1.0);
-                const double A =
-                    valid ? (k == s ? root(1, k) * root(0, k) : root(1, k) * root(1, s)) : 0.0;
-                const uint32_t sbase = (uint32_t)rank * (uint32_t)(M * M * kTile * 4);
-                for (int q = 0; q < M; ++q) {
-                    // root index of sqrt(m_q + 1) with m = n - e_k - e_s is 2 - d_q
-                    const int dq_ = (q == k) + (q == s);
-                    const double rq = root(2 - dq_, q);
-                    for (int l = 0; l < M; ++l) {
-                        const int dl_ = (l == k) + (l == s);
-                        const double B = q == l ? rq * root(3 - dq_, q) : rq * root(2 - dl_, l);
-                        const int32_t t =
-                            buf_ld_i32(r2, lane * 4, sbase + (uint32_t)((q * M + l) * kTile * 4));
-                        const double2 c = ldc(t);
-                        const double f = A * B;
-                        double vr = (cg.x * c.x + cg.y * c.y) * f;
-                        double vi = (cg.x * c.y - cg.y * c.x) * f;
-                        vr = wave_sum(vr);
-                        vi = wave_sum(vi);
-                        if (lane == 0) {
-                            const int e = p * M * M + q * M + l;
-                            acc[e].x += vr;
-                            acc[e].y += vi;
-                        }
-                    }
-                }
-                ++rank;
+        const __amdgpu_buffer_rsrc_t r1 =
+            make_rsrc(t1 + tile * NS * kTile, (uint32_t)(NS * kTile * 4));
+        int32_t t[CH];
+        double2 c[CH];
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            const int j = J0 + i, k = j / MT, l = j % MT;
+            if (k != l) t[i] = buf_ld_i32(r1, (uint32_t)((j * kTile + lane) * 4), 0);
+        }
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            const int j = J0 + i, k = j / MT, l = j % MT;
+            if (k != l) c[i] = ldc(t[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            const int j = J0 + i, k = j / MT, l = j % MT;
+            if (k == l) {
+                ar[i] = fma(cg.x * cg.x + cg.y * cg.y, (double)n[k], ar[i]);
+            } else {
+                const double f = sq[n[k]] * sq[n[l] + 1];
+                ar[i] = fma((cg.x * c[i].x + cg.y * c[i].y), f, ar[i]);
+                ai[i] = fma((cg.x * c[i].y - cg.y * c[i].x), f, ai[i]);
             }
         }
     }
-    __syncthreads();
-    for (int e = lane; e < E; e += kTile) part[(int64_t)wave * E + e] = acc[e];
+#pragma unroll
+    for (int i = 0; i < CH; ++i) {
+        const double vr = wave_sum(ar[i]), vi = wave_sum(ai[i]);
+        if (lane == 0) part[(int64_t)wave * NS + J0 + i] = make_double2(vr, vi);
+    }
+}
+
+template <int MT, typename OccT, bool BIGC, int... Js>
+__device__ __forceinline__ void rho1_all(std::integer_sequence<int, Js...>, int64_t D,
+                                         int64_t tiles, int nwaves, int wave,
+                                         const OccT *__restrict__ occ,
+                                         const int32_t *__restrict__ t1, const Gather<BIGC> &ldc,
+                                         const double *sq, double2 *__restrict__ part)
+{
+    (rho1_chunk<MT, OccT, BIGC, Js * kRhoChunk>(D, tiles, nwaves, wave, occ, t1, ldc, sq, part),
+     ...);
+}
+
+template <int MT, typename OccT, bool BIGC>
+__global__ __launch_bounds__(256) void k_rho1(int N, int64_t D, int64_t tiles, int nwaves,
+                                               const OccT *__restrict__ occ,
+                                               const int32_t *__restrict__ t1,
+                                               const double2 *__restrict__ C,
+                                               double2 *__restrict__ part)
+{
+    extern __shared__ double sq[];
+    fill_sqrt_table(sq, N + 3);
+    const int wave = blockIdx.x * 4 + wave_in_block();
+    if (wave >= nwaves) return;
+    const Gather<BIGC> ldc(C, D);
+    constexpr int NCH = (MT * MT + kRhoChunk - 1) / kRhoChunk;
+    rho1_all<MT, OccT, BIGC>(std::make_integer_sequence<int, NCH>{}, D, tiles, nwaves, wave, occ,
+                             t1, ldc, sq, part);
+}
+
+// rho2 for removal pair p = (k, s) (run-time), slots [J0, J0 + CH) of its
+// M*M creation pairs (compile-time).  The occupations of the lane's row are
+// also kept in LDS (occ_lds[m][lane]) so n_k, n_s need no register indexing.
+template <int MT, typename OccT, int J0>
+__device__ __forceinline__ void rho2_chunk(int k, int s, int p, int64_t D, int64_t tiles,
+                                           int nwaves, int wave, int64_t cap,
+                                           const OccT *__restrict__ occ,
+                                           const uint64_t *__restrict__ pmask,
+                                           const int64_t *__restrict__ t2_off,
+                                           const int32_t *__restrict__ t2,
+                                           const Gather<false> &ldc, const double *sq,
+                                           int *occ_lds, double2 *__restrict__ part)
+{
+    constexpr int NS = MT * MT;
+    constexpr int NP = MT * (MT + 1) / 2;
+    constexpr int W = (NP + 63) / 64;
+    constexpr int CH = NS - J0 < kRhoChunk ? NS - J0 : kRhoChunk;
+    const int lane = threadIdx.x & 63;
+    double ar[CH], ai[CH];
+#pragma unroll
+    for (int i = 0; i < CH; ++i) ar[i] = ai[i] = 0.0;
+    for (int64_t tile = wave; tile < tiles; tile += nwaves) {
+        const uint64_t *pm = pmask + tile * W;
+        if (!((pm[p >> 6] >> (p & 63)) & 1)) continue;   // no row of the tile can lose (k, s)
+        int64_t rank = 0;
+#pragma unroll
+        for (int wd = 0; wd < W; ++wd) {
+            const uint64_t word = pm[wd];
+            if (wd < (p >> 6)) rank += __popcll(word);
+            else if (wd == (p >> 6)) rank += __popcll(word & (((uint64_t)1 << (p & 63)) - 1));
+        }
+        int64_t off0, off1;
+        t2_block(t2_off, tile, cap, off0, off1);
+        const int64_t bs = off0 + rank * NS * kTile;
+        if (bs + NS * kTile > off1) continue;
+        const __amdgpu_buffer_rsrc_t r2 = make_rsrc(t2 + bs, (uint32_t)(NS * kTile * 4));
+        const int64_t g = tile * kTile + lane;
+        int n[MT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            n[m] = (int)occ[(tile * MT + m) * kTile + lane];
+            occ_lds[m * kTile + lane] = n[m];
+        }
+        int32_t t[CH];
+#pragma unroll
+        for (int i = 0; i < CH; ++i)
+            t[i] = buf_ld_i32(r2, (uint32_t)(((J0 + i) * kTile + lane) * 4), 0);
+        const double2 cg = ldc(g < D ? (int32_t)g : -1);
+        const int nk = occ_lds[k * kTile + lane], ns = occ_lds[s * kTile + lane];
+        const bool valid = k == s ? nk >= 2 : (nk >= 1 && ns >= 1);
+        const double A = valid ? sq[nk] * (k == s ? sq[max(nk - 1, 0)] : sq[ns]) : 0.0;
+        double2 c[CH];
+#pragma unroll
+        for (int i = 0; i < CH; ++i) c[i] = ldc(t[i]);
+        // conj(C_g) * A folded once per row
+        const double xr = cg.x * A, xi = -cg.y * A;
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            const int j = J0 + i, q = j / MT, l = j % MT;
+            // creation amplitudes on m = n - e_k - e_s (rows with A = 0 may go below 0)
+            const int mq = max(n[q] - (q == k) - (q == s), 0);
+            const int ml = max(n[l] - (l == k) - (l == s), 0);
+            const double B = q == l ? sq[mq + 1] * sq[mq + 2] : sq[mq + 1] * sq[ml + 1];
+            const double pr = xr * c[i].x - xi * c[i].y, pi = xr * c[i].y + xi * c[i].x;
+            ar[i] = fma(pr, B, ar[i]);
+            ai[i] = fma(pi, B, ai[i]);
+        }
+    }
+    constexpr int E = NP * NS;
+#pragma unroll
+    for (int i = 0; i < CH; ++i) {
+        const double vr = wave_sum(ar[i]), vi = wave_sum(ai[i]);
+        if (lane == 0) part[(int64_t)wave * E + p * NS + J0 + i] = make_double2(vr, vi);
+    }
+}
+
+template <int MT, typename OccT, int... Js>
+__device__ __forceinline__ void rho2_pair(std::integer_sequence<int, Js...>, int k, int s, int p,
+                                          int64_t D, int64_t tiles, int nwaves, int wave,
+                                          int64_t cap, const OccT *__restrict__ occ,
+                                          const uint64_t *__restrict__ pmask,
+                                          const int64_t *__restrict__ t2_off,
+                                          const int32_t *__restrict__ t2, const Gather<false> &ldc,
+                                          const double *sq, int *occ_lds,
+                                          double2 *__restrict__ part)
+{
+    (rho2_chunk<MT, OccT, Js * kRhoChunk>(k, s, p, D, tiles, nwaves, wave, cap, occ, pmask, t2_off,
+                                          t2, ldc, sq, occ_lds, part),
+     ...);
+}
+
+// Dynamic LDS: sqrt table (N+3 doubles), then per wavefront an int
+// occupation row [M][64].
+template <int MT, typename OccT>
+__global__ __launch_bounds__(256) void k_rho2(int N, int64_t D, int64_t tiles, int nwaves,
+                                               int64_t cap, const OccT *__restrict__ occ,
+                                               const uint64_t *__restrict__ pmask,
+                                               const int64_t *__restrict__ t2_off,
+                                               const int32_t *__restrict__ t2,
+                                               const double2 *__restrict__ C,
+                                               double2 *__restrict__ part)
+{
+    extern __shared__ double sq[];
+    fill_sqrt_table(sq, N + 3);
+    int *occ_lds = (int *)(sq + N + 3) + wave_in_block() * MT * kTile;
+    const int wave = blockIdx.x * 4 + wave_in_block();
+    if (wave >= nwaves) return;
+    const Gather<false> ldc(C, D);
+    constexpr int NCH = (MT * MT + kRhoChunk - 1) / kRhoChunk;
+    int p = 0;
+#pragma unroll 1
+    for (int k = 0; k < MT; ++k) {
+#pragma unroll 1
+        for (int s = k; s < MT; ++s, ++p)
+            rho2_pair<MT, OccT>(std::make_integer_sequence<int, NCH>{}, k, s, p, D, tiles, nwaves,
+                                wave, cap, occ, pmask, t2_off, t2, ldc, sq, occ_lds, part);
+    }
 }
 
 // out[e] = sum over waves of part[w][e], in increasing w.
@@ -669,25 +802,34 @@ static int apply_common(int32_t N, int32_t M, const double *h_d, const double *g
                        (const double2 *)h_d, gp, hp);
     const int64_t nblocks = (t->tiles + 3) / 4;
     const bool big = D * 16 > (int64_t)0xFFFFFFFFu;
+    // Instantiated combinations: 16-bit occupations only for M <= 5 (M >= 6
+    // with N > 255 has D > 2^31), 64-bit gathers (D >= 2^28) only without the
+    // double-jump map (a double-jump map of that size cannot fit in HBM).
+    bool launched = false;
 #define MC_APPLY_LAUNCH(OT, BIG)                                                               \
     if (M <= 8) {                                                                              \
-        MC_DISPATCH_M(M, if constexpr (MT > 0) hipLaunchKernelGGL(                              \
-                             (k_apply<MT, OT, BIG>), dim3(nblocks), dim3(256), 0, s, D,         \
-                             t->tiles, nblocks, t->t2_entries, (const OT *)t->occ_d, t->t1_d,   \
-                             t->pmask_d, t->t2_off_d, t->t2_d, (const double2 *)hp,             \
-                             (const double2 *)gp, (const double2 *)C_d, (double2 *)HC_d));     \
+        MC_DISPATCH_M(M, if constexpr (MT > 0 && !BIG && (MT <= 5 || sizeof(OT) == 1)) {        \
+            hipLaunchKernelGGL((k_apply<MT, OT, BIG>), dim3(nblocks), dim3(256), 0, s, D,        \
+                               t->tiles, nblocks, t->t2_entries, (const OT *)t->occ_d, t->t1_d,  \
+                               t->pmask_d, t->t2_off_d, t->t2_d, (const double2 *)hp,            \
+                               (const double2 *)gp, (const double2 *)C_d, (double2 *)HC_d);     \
+            launched = true;                                                                   \
+        });                                                                                    \
     } else {                                                                                   \
         hipLaunchKernelGGL((k_apply_generic<OT, BIG>), dim3(t->tiles), dim3(64),                \
                            (size_t)5 * M * kTile * 8, s, M, D, t->tiles, t->t2_entries,        \
                            (const OT *)t->occ_d, t->t1_d, t->pmask_d, t->t2_off_d, t->t2_d,    \
                            (const double2 *)hp, (const double2 *)gp, (const double2 *)C_d,     \
                            (double2 *)HC_d);                                                   \
+        launched = true;                                                                       \
     }
 #define MC_CHAINED_LAUNCH(OT, BIG)                                                             \
-    MC_DISPATCH_M(M, if constexpr (MT > 0) hipLaunchKernelGGL(                                  \
-                         (k_apply_chained<MT, OT, BIG>), dim3(nblocks), dim3(256), 0, s, D,     \
-                         t->tiles, nblocks, (const OT *)t->occ_d, t->t1_d, (const double2 *)hp, \
-                         (const double2 *)gp, (const double2 *)C_d, (double2 *)HC_d))
+    MC_DISPATCH_M(M, if constexpr (MT > 0 && (MT <= 5 || sizeof(OT) == 1)) {                     \
+        hipLaunchKernelGGL((k_apply_chained<MT, OT, BIG>), dim3(nblocks), dim3(256), 0, s, D,    \
+                           t->tiles, nblocks, (const OT *)t->occ_d, t->t1_d, (const double2 *)hp, \
+                           (const double2 *)gp, (const double2 *)C_d, (double2 *)HC_d);         \
+        launched = true;                                                                       \
+    })
     if (chained) {
         if (occ_width(N) == 1) {
             if (big) { MC_CHAINED_LAUNCH(uint8_t, true); } else { MC_CHAINED_LAUNCH(uint8_t, false); }
@@ -699,8 +841,8 @@ static int apply_common(int32_t N, int32_t M, const double *h_d, const double *g
     } else {
         if (big) { MC_APPLY_LAUNCH(uint16_t, true); } else { MC_APPLY_LAUNCH(uint16_t, false); }
     }
-#undef MC_CHAINED_LAUNCH
 #undef MC_APPLY_LAUNCH
+    if (!launched) return MC_EINVAL;
     return launch_status();
 }
 
@@ -733,16 +875,28 @@ int mc_rho1(int32_t N, int32_t M, const mc_tables *t, const double *C_d, double 
     const int nw = rho_waves(t->tiles);
     const bool big = D * 16 > (int64_t)0xFFFFFFFFu;
     double2 *part = (double2 *)ws_d;
-#define MC_RHO1_LAUNCH(OT, BIG)                                                               \
-    MC_DISPATCH_M(M, hipLaunchKernelGGL((k_rho1<MT, OT, BIG>), dim3((nw + 3) / 4), dim3(256), 0, \
-                                        s, M, D, t->tiles, nw, (const OT *)t->occ_d, t->t1_d,  \
-                                        (const double2 *)C_d, part))
+    bool launched = false;
+#define MC_RHO1_LAUNCH(OT, BIG)                                                                 \
+    MC_DISPATCH_M(M, if constexpr (MT > 0 && (MT <= 5 || sizeof(OT) == 1)) {                      \
+        hipLaunchKernelGGL((k_rho1<MT, OT, BIG>), dim3((nw + 3) / 4), dim3(256), sqb, s, N, D,    \
+                           t->tiles, nw, (const OT *)t->occ_d, t->t1_d, (const double2 *)C_d,     \
+                           part);                                                                \
+        launched = true;                                                                         \
+    } else if constexpr (MT == 0) {                                                              \
+        hipLaunchKernelGGL((k_rho1_generic<0, OT, BIG>), dim3((nw + 3) / 4), dim3(256), 0, s, M,  \
+                           D, t->tiles, nw, (const OT *)t->occ_d, t->t1_d, (const double2 *)C_d,  \
+                           part);                                                                \
+        launched = true;                                                                         \
+    })
+    const size_t sqb = (size_t)(N + 3) * 8;
+    if (sqb > 65536) return MC_EINVAL;
     if (occ_width(N) == 1) {
         if (big) { MC_RHO1_LAUNCH(uint8_t, true); } else { MC_RHO1_LAUNCH(uint8_t, false); }
     } else {
         if (big) { MC_RHO1_LAUNCH(uint16_t, true); } else { MC_RHO1_LAUNCH(uint16_t, false); }
     }
 #undef MC_RHO1_LAUNCH
+    if (!launched) return MC_EINVAL;
     const int E = M * M;
     hipLaunchKernelGGL(k_rho1_finalize, dim3((E + 255) / 256), dim3(256), 0, s, E, nw, part,
                        (double2 *)rho1_d);
@@ -765,19 +919,24 @@ int mc_rho2(int32_t N, int32_t M, const mc_tables *t, const double *C_d, double 
     const int nw = rho_waves(t->tiles);
     const bool big = D * 16 > (int64_t)0xFFFFFFFFu;
     double2 *part = (double2 *)ws_d;
-#define MC_RHO2_LAUNCH(OT, BIG)                                                          \
-    hipLaunchKernelGGL((k_rho2<OT, BIG>), dim3(nw), dim3(64), lds, s, M, D, t->tiles, nw, \
-                       t->t2_entries,                                                      \
-                       (const OT *)t->occ_d, t->pmask_d, t->t2_off_d, t->t2_d,             \
-                       (const double2 *)C_d, part)
-    const size_t lds = (size_t)5 * M * kTile * 8 + (size_t)npairs(M) * M * M * 16;
-    if (lds > 65536) return MC_EINVAL;   // M <= 8 fits
+    bool launched = false;
+#define MC_RHO2_LAUNCH(OT)                                                                      \
+    MC_DISPATCH_M(M, if constexpr (MT > 0 && (MT <= 5 || sizeof(OT) == 1)) {                      \
+        hipLaunchKernelGGL((k_rho2<MT, OT>), dim3((nw + 3) / 4), dim3(256), lds, s, N, D,          \
+                           t->tiles, nw, t->t2_entries, (const OT *)t->occ_d, t->pmask_d,         \
+                           t->t2_off_d, t->t2_d, (const double2 *)C_d, part);                    \
+        launched = true;                                                                         \
+    })
+    const size_t lds = (size_t)(N + 3) * 8 + (size_t)4 * M * kTile * 4;
+    // the double-jump map cannot exist for D >= 2^28 (it would exceed HBM)
+    if (M > 8 || lds > 65536 || big) return MC_EINVAL;
     if (occ_width(N) == 1) {
-        if (big) { MC_RHO2_LAUNCH(uint8_t, true); } else { MC_RHO2_LAUNCH(uint8_t, false); }
+        MC_RHO2_LAUNCH(uint8_t);
     } else {
-        if (big) { MC_RHO2_LAUNCH(uint16_t, true); } else { MC_RHO2_LAUNCH(uint16_t, false); }
+        MC_RHO2_LAUNCH(uint16_t);
     }
 #undef MC_RHO2_LAUNCH
+    if (!launched) return MC_EINVAL;
     const int total = M * M * M * M;
     hipLaunchKernelGGL(k_rho2_finalize, dim3((total + 255) / 256), dim3(256), 0, s, M, nw, part,
                        (double2 *)rho2_d);
