@@ -161,22 +161,33 @@ def batched_leg(dev, steps: int = 50) -> dict:
         tab = mc.build_tables(N, M, dev, double_jumps=t2)
         insts.append((tab, torch.from_numpy(h).to(dev), torch.from_numpy(g).to(dev)))
     total_dim = sum(t.dim for t, _, _ in insts)
+    print(f"[bench] batched: {len(insts)} instances, total dim {total_dim}; autotuning",
+          file=sys.stderr, flush=True)
     tuned = autotune.tune(insts, cache_path=os.path.join(ROOT, "gpurun_out", "autotune_cache.json"),
                           reps=2)
+    print(f"[bench] batched: schedule {tuned['schedule']}", file=sys.stderr, flush=True)
     b = Batch(insts, tuned["schedule"])
+    apply_ms = autotune.time_schedule(insts, tuned["schedule"], reps=3)
     rng = np.random.default_rng(9)
     v0 = b.vector()
     for i, (t, _, _) in enumerate(insts):
         b.segment(v0, i).copy_(torch.from_numpy(W.random_coefficients(rng, t.dim)).to(dev))
+    print(f"[bench] batched: one apply {apply_ms:.1f} ms; capturing {steps} Lanczos steps",
+          file=sys.stderr, flush=True)
     lz = BatchedLanczos(b, steps, graph=True)
     a_b, be_b = lz.run(v0)                       # warm replay
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     a_b, be_b = lz.run(v0)
-    t_batch = time.perf_counter() - t0
     torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    print(f"[bench] batched: graph replay {t_batch:.2f} s; per-instance plain runs",
+          file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     worst = 0.0
     for i, (t, hd, gd) in enumerate(insts):
+        if i % 16 == 0:
+            print(f"[bench] batched: plain instance {i}/{len(insts)}", file=sys.stderr, flush=True)
         a_p, b_p = plain_lanczos(t, hd, gd, b.segment(v0, i).contiguous(), steps)
         torch.cuda.synchronize()
         k = min(steps, t.dim - 1, 8)
@@ -187,6 +198,7 @@ def batched_leg(dev, steps: int = 50) -> dict:
     out = {"instances": len(insts), "total_dim": int(total_dim),
            "with_double_jump_map": int(sum(use_t2)), "steps": steps,
            "schedule": tuned["schedule"], "schedule_cached": tuned["cached"],
+           "batched_apply_ms": apply_ms,
            "batched_graph_s": t_batch, "plain_eager_s": t_plain,
            "batched_instance_applies_per_s": len(insts) * steps / t_batch,
            "plain_instance_applies_per_s": len(insts) * steps / t_plain,

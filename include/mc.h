@@ -108,7 +108,20 @@ int mc_unhash(int32_t N, int32_t M, int64_t index, int32_t *occ);
  * valid removal pair in lexicographic order, slot q*M + l.  Only the memory
  * order differs: tiles are stored slot-major so that 64 consecutive rows
  * read 64 consecutive entries.
+ *
+ * Reduced form (t->form == MC_FORM_REDUCED).  A slot whose creation pair
+ * {q, l} shares an orbital with the removal pair {k, s} leads back to the row
+ * itself or to a single jump (the coincident-index cases of the appendix on
+ * matrix elements), and slots (q, l) and (l, q) lead to the same
+ * configuration.  The reduced map keeps one entry per true double jump: the
+ * block of pair (k, s) holds nd(k, s) * 64 entries, slot r being the r-th
+ * creation pair (q, l), q <= l, q and l both outside {k, s}, in
+ * lexicographic order; nd = M(M-1)/2 for k = s and (M-1)(M-2)/2 for k < s
+ * (110 entries per full row at M = 5 instead of 375).  Offsets, pair mask
+ * and padding follow the same rules with these block sizes.
  */
+#define MC_FORM_PAPER 0     /* double-jump map as in the paper (M^2 slots per pair) */
+#define MC_FORM_REDUCED 1   /* true double jumps only (see above) */
 typedef struct mc_table_sizes {
     int64_t dim;            /* D */
     int64_t tiles;          /* ceil(D / 64) */
@@ -121,6 +134,9 @@ typedef struct mc_table_sizes {
     int64_t t2_off_bytes;
     int64_t t2_compact_entries; /* entries of the paper's packed rows:
                                    M^2 * M(M+1)/2 * N_c(N-2, M) */
+    int64_t t2r_compact_entries; /* entries of the reduced rows:
+                                    [M * M(M-1)/2 + M(M-1)/2 * (M-1)(M-2)/2]
+                                    * N_c(N-2, M) */
 } mc_table_sizes;
 
 /* Sizes of every table for (N, M).  Host only.  MC_ERANGE if D >= 2^31. */
@@ -137,16 +153,21 @@ typedef struct mc_tables {
     int32_t *t2_d;           /* may be NULL until mc_build_double_jumps */
     int64_t t2_entries;      /* capacity of t2_d, in entries */
     int64_t t2_required;     /* set by mc_build_jump_tables */
+    int32_t form;            /* MC_FORM_PAPER or MC_FORM_REDUCED; set before
+                                mc_build_jump_tables (it fixes t2_off) */
+    int32_t reserved;
 } mc_tables;
 
 /* Builds binom, occ, t1, pmask and t2_off into the caller's buffers (sizes
- * from mc_tables_size; t->N, t->M must match).  Synchronises `stream` once
- * at the end to read t2_off[tiles] into t->t2_required (entries the double
- * jump map needs).  MC_EINVAL on a missing buffer or mismatched N/M. */
+ * from mc_tables_size; t->N, t->M must match; t->form picks the block sizes
+ * of t2_off).  Synchronises `stream` once at the end to read t2_off[tiles]
+ * into t->t2_required (entries the double jump map needs).  MC_EINVAL on a
+ * missing buffer, mismatched N/M or an unknown form. */
 int mc_build_jump_tables(int32_t N, int32_t M, mc_tables *t, mc_stream stream);
 
-/* Fills t->t2_d.  Needs a completed mc_build_jump_tables on the same tables
- * and t->t2_entries >= t->t2_required (else MC_ENOMEM). */
+/* Fills t->t2_d in the tables' form.  Needs a completed mc_build_jump_tables
+ * on the same tables (same form) and t->t2_entries >= t->t2_required (else
+ * MC_ENOMEM). */
 int mc_build_double_jumps(int32_t N, int32_t M, const mc_tables *t, mc_stream stream);
 
 /* Device-side hash / unhash of many configurations, row-major int32
@@ -161,7 +182,7 @@ int mc_unhash_batch(int32_t N, int32_t M, const mc_tables *t, const int64_t *ind
 /* Reads the double-jump map entry for (row, k, s, q, l) of each query
  * (queries_d[count][5] int64: row, k, s, q, l with any k, s order) into
  * out_d[count]; -1 where the removal is not possible.  A test and debugging
- * accessor for the tiled layout. */
+ * accessor for the tiled layout; paper form only (MC_EINVAL otherwise). */
 int mc_t2_lookup(int32_t N, int32_t M, const mc_tables *t, const int64_t *queries_d,
                  int32_t *out_d, int64_t count, mc_stream stream);
 
@@ -187,6 +208,21 @@ int mc_workspace_size(int32_t N, int32_t M, int32_t op, size_t *bytes);
  * q = l).  If the tables were built without the double-jump map
  * (t->t2_d == NULL), each double-jump target is found as two chained single
  * jumps, T1[T1[g][k][q]][s][l] (M <= 8), and no double-jump table is read.
+ *
+ * Tables in the reduced form (M <= 8) evaluate the same sum case by case:
+ * slots with {q,l} = {k,s} add to the row's own coefficient, slots sharing
+ * one orbital add to the single-jump coefficients, and only the true double
+ * jumps are gathered (reduced map, or chained single jumps without it):
+ *   (H C)_g = [sum_k n_k (h_kk - I_kk) + sum_{k<=s} n_k n_s I_ks] C_g
+ *           + sum_{a != b} sqrt(n_a (n_b+1)) [h_ab - S_aba + sum_c n_c S_abc]
+ *                                                       C[t1[g][a][b]]
+ *           + sum_{valid k<=s} A_ks sum_{q<=l outside {k,s}} B_ql(n) R_ks,ql
+ *                                                       C[reduced slot]
+ * with g' = G'/2 the staged pair coefficients, I_ks = g'_{ks,ks} + g'_{ks,sk}
+ * (k < s) or g'_{kk,kk}; S_abc = g'_{ac,cb} + g'_{ac,bc} (c != b) or
+ * g'_{ab,bb}, taken over the unordered pair {a, c}; R_ks,ql = g'_{ks,ql} +
+ * g'_{ks,lq} (q < l) or g'_{ks,qq}.  Sums agree with the paper form up to
+ * rounding order.
  * h_d [M*M], g_d [M^4], C_d and HC_d [D] complex128 on the device;
  * HC_d must not overlap C_d (MC_EINVAL).  ws_d: mc_workspace_size(APPLY);
  * the call stages h and G' there, so concurrent calls need separate ws.
@@ -209,7 +245,8 @@ int mc_rho1(int32_t N, int32_t M, const mc_tables *t, const double *C_d,
             double *rho1_d, void *ws_d, size_t ws_bytes, mc_stream stream);
 
 /* rho2_d [M^4] = <a+_k a+_s a_q a_l> (Eq. rho2) through the double-jump map,
- * deterministic fixed-order reduction in ws_d (mc_workspace_size(RHO2)). */
+ * deterministic fixed-order reduction in ws_d (mc_workspace_size(RHO2)).
+ * Needs a paper-form double-jump map (MC_EINVAL otherwise). */
 int mc_rho2(int32_t N, int32_t M, const mc_tables *t, const double *C_d,
             double *rho2_d, void *ws_d, size_t ws_bytes, mc_stream stream);
 
@@ -240,10 +277,13 @@ int mc_zaxpby(int64_t n, const double *a_d, const double *x_d, const double *b_d
  * once.  A batch vector is the concatenation of the instances' coefficient
  * vectors in the order the caller lists them (instance i at offset
  * sum_{j<i} D_j, total mc_batch_vector_length()).  Instances are grouped by
- * orbital count; each group runs as one persistent kernel whose wavefronts
- * walk the group's (instance, 64-row tile) work list.  An instance whose
- * tables hold a double-jump map uses it; one built without it (t2_d == NULL)
- * chains two single jumps.  Limits per instance: M <= 8, N <= 255, D < 2^28.
+ * orbital count and by how their tiles run (paper or reduced form, with or
+ * without a double-jump map); each group runs as one persistent kernel whose
+ * wavefronts walk the group's (instance, 64-row tile) work list.  An
+ * instance whose tables hold a double-jump map uses it; one built without it
+ * (t2_d == NULL) chains two single jumps; reduced-form tables run the
+ * case-split sum of mc_apply_H.  Limits per instance: M <= 8, N <= 255,
+ * D < 2^28.
  *
  * Every batch call only enqueues kernels on `stream` (no host
  * synchronisation, no memset), so sequences of calls can be captured into a

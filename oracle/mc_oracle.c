@@ -359,6 +359,66 @@ void orc_t2_rows(int32_t N, int32_t M, const int64_t *rows, int64_t nrows,
     }
 }
 
+/* Reduced double-jump map: only the true double jumps.  A term
+ * a+_q a+_l a_s a_k of the two-body sum whose creation pair {q, l} shares an
+ * orbital with the removal pair {k, s} lands on the row itself or on a
+ * single jump (the coincident-index cases of the appendix on matrix
+ * elements; the footnote on density-matrix cost notes that no index
+ * conversion is needed there).  This map keeps the rest: for each valid
+ * removal pair (k, s), k <= s, in lexicographic order, the creation pairs
+ * (q, l), q <= l, with q and l both outside {k, s}, in lexicographic order;
+ * each entry is the index of n - e_k - e_s + e_q + e_l (Algorithm 1). */
+static int64_t reduced_pair_slots(int32_t M, const int32_t *n)
+{
+    int64_t c = 0;
+    for (int32_t k = 0; k < M; ++k)
+        for (int32_t s = k; s < M; ++s) {
+            int valid = (k == s) ? (n[k] >= 2) : (n[k] >= 1 && n[s] >= 1);
+            if (!valid) continue;
+            for (int32_t q = 0; q < M; ++q)
+                for (int32_t l = q; l < M; ++l)
+                    if (q != k && q != s && l != k && l != s) ++c;
+        }
+    return c;
+}
+
+void orc_t2r_row_lengths(int32_t N, int32_t M, const int64_t *rows,
+                         int64_t nrows, int64_t *len)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < nrows; ++r) {
+        int32_t n[ORC_MAXM];
+        orc_unhash(N, M, rows[r], n);
+        len[r] = reduced_pair_slots(M, n);
+    }
+}
+
+void orc_t2r_rows(int32_t N, int32_t M, const int64_t *rows, int64_t nrows,
+                  const int64_t *offsets, int32_t *t2r)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < nrows; ++r) {
+        int32_t n0[ORC_MAXM], n[ORC_MAXM];
+        orc_unhash(N, M, rows[r], n0);
+        int32_t *dst = t2r + offsets[r];
+        for (int32_t k = 0; k < M; ++k)
+            for (int32_t s = k; s < M; ++s) {
+                int valid = (k == s) ? (n0[k] >= 2) : (n0[k] >= 1 && n0[s] >= 1);
+                if (!valid) continue;
+                for (int32_t q = 0; q < M; ++q)
+                    for (int32_t l = q; l < M; ++l) {
+                        if (q == k || q == s || l == k || l == s) continue;
+                        memcpy(n, n0, sizeof(int32_t) * M);
+                        n[k] -= 1;
+                        n[s] -= 1;
+                        n[q] += 1;
+                        n[l] += 1;
+                        *dst++ = (int32_t)orc_hash(N, M, n);
+                    }
+            }
+    }
+}
+
 /* Hash a list of occupation vectors with Algorithm 1. */
 void orc_hash_rows(int32_t N, int32_t M, const int32_t *occ, int64_t nrows,
                    int64_t *idx)

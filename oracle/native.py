@@ -54,6 +54,8 @@ def _load():
             lib.orc_t1_rows.argtypes = [i32, i32, p, i64, p]
             lib.orc_t2_row_lengths.argtypes = [i32, i32, p, i64, p]
             lib.orc_t2_rows.argtypes = [i32, i32, p, i64, p, p]
+            lib.orc_t2r_row_lengths.argtypes = [i32, i32, p, i64, p]
+            lib.orc_t2r_rows.argtypes = [i32, i32, p, i64, p, p]
             lib.orc_hash_rows.argtypes = [i32, i32, p, i64, p]
             _lib = lib
     return _lib
@@ -135,6 +137,25 @@ def t2_rows(N: int, M: int, rows=None):
     np.cumsum(lens, out=off[1:])
     ent = np.empty(int(off[-1]), dtype=np.int32)
     _load().orc_t2_rows(N, M, _ptr(rows), rows.size, _ptr(off), _ptr(ent))
+    return off, ent
+
+
+def t2r_row_lengths(N: int, M: int, rows=None) -> np.ndarray:
+    rows = _rows(rows, dim(N, M))
+    out = np.empty(rows.size, dtype=np.int64)
+    _load().orc_t2r_row_lengths(N, M, _ptr(rows), rows.size, _ptr(out))
+    return out
+
+
+def t2r_rows(N: int, M: int, rows=None):
+    """Reduced double-jump map rows (true double jumps only: creation pairs
+    q <= l outside the removal pair).  Returns (offsets int64, entries int32)."""
+    rows = _rows(rows, dim(N, M))
+    lens = t2r_row_lengths(N, M, rows)
+    off = np.zeros(rows.size + 1, dtype=np.int64)
+    np.cumsum(lens, out=off[1:])
+    ent = np.empty(int(off[-1]), dtype=np.int32)
+    _load().orc_t2r_rows(N, M, _ptr(rows), rows.size, _ptr(off), _ptr(ent))
     return off, ent
 
 

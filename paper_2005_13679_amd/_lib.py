@@ -37,6 +37,11 @@ MC_CONJ_Y = 8
 c_i32, c_i64, c_p, c_sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t
 
 
+MC_FORM_PAPER = 0     # double-jump map with M*M slots per removal pair (the paper's)
+MC_FORM_REDUCED = 1   # true double jumps only; apply in the case-split form
+FORMS = {"paper": MC_FORM_PAPER, "reduced": MC_FORM_REDUCED}
+
+
 class TableSizes(ctypes.Structure):
     _fields_ = [
         ("dim", c_i64),
@@ -49,6 +54,7 @@ class TableSizes(ctypes.Structure):
         ("pmask_bytes", c_i64),
         ("t2_off_bytes", c_i64),
         ("t2_compact_entries", c_i64),
+        ("t2r_compact_entries", c_i64),
     ]
 
 
@@ -66,6 +72,8 @@ class CTables(ctypes.Structure):
         ("t2_d", c_p),
         ("t2_entries", c_i64),
         ("t2_required", c_i64),
+        ("form", c_i32),
+        ("reserved", c_i32),
     ]
 
 

@@ -85,13 +85,17 @@ class Tables:
     Buffers are torch tensors owned by this object; ``c`` is the C descriptor
     passed to the library."""
 
-    def __init__(self, N: int, M: int, device=None, double_jumps: bool = True):
+    def __init__(self, N: int, M: int, device=None, double_jumps: bool = True,
+                 form: str = "paper"):
         device = torch.device(device if device is not None else "cuda")
         if device.type != "cuda":
             raise ValueError("tables live in GPU memory")
         if device.index is None:
             device = torch.device("cuda", torch.cuda.current_device())
+        if form not in L.FORMS:
+            raise ValueError(f"form must be one of {sorted(L.FORMS)}")
         self.N, self.M, self.device = int(N), int(M), device
+        self.form = form
         sz = tables_size(N, M)
         self.sizes = sz
         self.dim, self.tiles = int(sz.dim), int(sz.tiles)
@@ -116,6 +120,7 @@ class Tables:
         c.t2_d = None
         c.t2_entries = 0
         c.t2_required = -1
+        c.form = L.FORMS[form]
         self.c = c
         with torch.cuda.device(device):
             L.check(L.load().mc_build_jump_tables(N, M, ctypes.byref(c), _stream(device)),
@@ -172,8 +177,13 @@ class Tables:
         return t.transpose(0, 3, 1, 2).reshape(-1, self.M, self.M)[: self.dim]
 
 
-def build_tables(N: int, M: int, device=None, double_jumps: bool = True) -> Tables:
-    return Tables(N, M, device, double_jumps)
+def build_tables(N: int, M: int, device=None, double_jumps: bool = True,
+                 form: str = "paper") -> Tables:
+    """Tables of (N, M).  form="paper": the paper's double-jump map (M*M
+    slots per removal pair); form="reduced": only the true double jumps, and
+    H.C runs in the case-split form.  double_jumps=False builds no map (the
+    apply then chains single jumps)."""
+    return Tables(N, M, device, double_jumps, form)
 
 
 # ---------------------------------------------------------------------------

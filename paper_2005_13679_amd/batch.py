@@ -18,22 +18,27 @@ from . import _lib as L
 from . import api
 
 
-def table_bytes(N: int, M: int, double_jumps: bool) -> int:
+def table_bytes(N: int, M: int, double_jumps: bool, form: str = "paper") -> int:
     """Device bytes of the tables of one instance (double-jump map included
-    only if requested; its tiled size is bounded by the compact size plus one
-    64-row block per pair and tile)."""
+    only if requested; its tiled size is estimated as the packed size plus an
+    eighth of a 64-row block per pair and tile for padding)."""
     s = api.tables_size(N, M)
     b = s.binom_bytes + s.occ_bytes_total + s.t1_bytes + s.pmask_bytes + s.t2_off_bytes
     if double_jumps:
-        b += 4 * s.t2_compact_entries + 4 * s.tiles * (M * (M + 1) // 2) * M * M * 64 // 8
+        if form == "reduced":
+            per_tile = M * (M * (M - 1) // 2) + (M * (M - 1) // 2) * ((M - 1) * (M - 2) // 2)
+            b += 4 * s.t2r_compact_entries + 4 * s.tiles * per_tile * 64 // 8
+        else:
+            b += 4 * s.t2_compact_entries + 4 * s.tiles * (M * (M + 1) // 2) * M * M * 64 // 8
     return int(b)
 
 
-def choose_double_jumps(shapes, budget_bytes: float) -> list[bool]:
+def choose_double_jumps(shapes, budget_bytes: float, form: str = "paper") -> list[bool]:
     """Which instances keep a double-jump map within `budget_bytes` of
     double-jump tables: smallest maps first (most instances served); the rest
     chain single jumps."""
-    sizes = [(table_bytes(N, M, True) - table_bytes(N, M, False), i) for i, (N, M) in enumerate(shapes)]
+    sizes = [(table_bytes(N, M, True, form) - table_bytes(N, M, False, form), i)
+             for i, (N, M) in enumerate(shapes)]
     use = [False] * len(shapes)
     left = float(budget_bytes)
     for sz, i in sorted(sizes):

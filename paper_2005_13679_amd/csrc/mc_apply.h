@@ -15,6 +15,13 @@
 #ifndef MC_APPLY_WAVES
 #define MC_APPLY_WAVES 2
 #endif
+// Double-jump index loads: 0 = each batch loads its indices, then gathers;
+// 1 = the next batch's indices are loaded while the current batch's gathers
+// are in flight (within a pair); 2 = also the first batch of the next block
+// (across pairs, and the first block during the one-body part).
+#ifndef MC_T2_PIPELINE
+#define MC_T2_PIPELINE 2
+#endif
 
 namespace mc {
 
@@ -41,27 +48,71 @@ struct Gather {
     }
 };
 
-// Per-row square roots of small integers used by the jump amplitudes.
-template <int MA>
-struct Roots {
-    double s0[MA], sm1[MA], sp1[MA], sp2[MA];
+// Per-row square roots of small integers used by the jump amplitudes:
+// root<d>(m) = sqrt(n_m + d) for d in {-1, 0, 1, 2} (0 where n_m + d < 0).
+// For M <= 5 the four tables live in registers; for M >= 6 (where they would
+// cost 8M VGPRs) only the occupations do and the roots come from an LDS table
+// of sqrt(i), i = 0 .. N+2, filled once per block.
+template <int MT>
+constexpr bool kLdsRoots = MT >= 6;
+
+template <int MT, bool LDS = kLdsRoots<MT>>
+struct RowSq;
+
+template <int MT>
+struct RowSq<MT, false> {
+    double sm1[MT], s0[MT], sp1[MT], sp2[MT];
+    __device__ __forceinline__ void init(const int (&n)[MT], const double *)
+    {
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            const double x = (double)n[m];
+            s0[m] = sqrt(x);
+            sm1[m] = sqrt(x > 1.0 ? x - 1.0 : 0.0);
+            sp1[m] = sqrt(x + 1.0);
+            sp2[m] = sqrt(x + 2.0);
+        }
+    }
+    template <int d>
+    __device__ __forceinline__ double root(int m) const
+    {
+        static_assert(d >= -1 && d <= 2, "root offset");
+        return d == -1 ? sm1[m] : (d == 0 ? s0[m] : (d == 1 ? sp1[m] : sp2[m]));
+    }
 };
 
-template <int MT, typename OccT>
-__device__ __forceinline__ void load_row(const OccT *__restrict__ occ, int64_t tile, int M,
-                                         int lane, int *n, Roots<(MT > 0 ? MT : MC_MAX_M)> &R)
-{
-    constexpr int MA = MT > 0 ? MT : MC_MAX_M;
-#pragma unroll (kUnroll<MT>)
-    for (int m = 0; m < MA; ++m) {
-        if (MT == 0 && m >= M) break;
-        n[m] = (int)occ[(tile * M + m) * kTile + lane];
-        const double x = (double)n[m];
-        R.s0[m] = sqrt(x);
-        R.sm1[m] = sqrt(x > 1.0 ? x - 1.0 : 0.0);
-        R.sp1[m] = sqrt(x + 1.0);
-        R.sp2[m] = sqrt(x + 2.0);
+template <int MT>
+struct RowSq<MT, true> {
+    int nn[MT];
+    const double *sq;
+    __device__ __forceinline__ void init(const int (&n)[MT], const double *tab)
+    {
+#pragma unroll
+        for (int m = 0; m < MT; ++m) nn[m] = n[m];
+        sq = tab;
     }
+    template <int d>
+    __device__ __forceinline__ double root(int m) const
+    {
+        const int i = nn[m] + d;
+        return sq[i > 0 ? i : 0];
+    }
+};
+
+// sqrt(i) for i = 0 .. n-1 into LDS (block-wide; every thread must call it)
+__device__ __forceinline__ void fill_sqrt_table(double *tab, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) tab[i] = sqrt((double)i);
+    __syncthreads();
+}
+
+template <int MT, typename OccT>
+__device__ __forceinline__ void load_row(const OccT *__restrict__ occ, int64_t tile, int lane,
+                                         int (&n)[MT], RowSq<MT> &R, const double *sq)
+{
+#pragma unroll
+    for (int m = 0; m < MT; ++m) n[m] = (int)occ[(tile * MT + m) * kTile + lane];
+    R.init(n, sq);
 }
 
 // Removal pair p (lexicographic k <= s) -> (k, s), for compile-time use.
@@ -128,14 +179,23 @@ __device__ __forceinline__ void pair_batches(const int32_t *t2, int64_t pos, int
     if constexpr (B < NB) {
         constexpr int NS = MT * MT, SB = kSlotBatch<MT>, J0 = B * SB;
         double2 c[SB];
+        if constexpr (MC_T2_PIPELINE == 0) {
+            // indices of this batch, then its gathers
+            load_t2_batch<MT, SB, J0>(tn, r2, lane);
 #pragma unroll
-        for (int i = 0; i < SB; ++i)
-            if (J0 + i < NS) c[i] = ldc(B == 0 ? tf[i] : tn[i]);
-        if constexpr (B + 1 < NB) {
-            load_t2_batch<MT, SB, J0 + SB>(tn, r2, lane);
+            for (int i = 0; i < SB; ++i)
+                if (J0 + i < NS) c[i] = ldc(tn[i]);
         } else {
-            const __amdgpu_buffer_rsrc_t rn = t2_block_rsrc(t2, pos + NS * kTile, off1, NS);
-            load_t2_batch<MT, SB, 0>(tf, rn, lane);
+            if constexpr (MC_T2_PIPELINE == 1 && B == 0) load_t2_batch<MT, SB, 0>(tf, r2, lane);
+#pragma unroll
+            for (int i = 0; i < SB; ++i)
+                if (J0 + i < NS) c[i] = ldc(B == 0 ? tf[i] : tn[i]);
+            if constexpr (B + 1 < NB) {
+                load_t2_batch<MT, SB, J0 + SB>(tn, r2, lane);
+            } else if constexpr (MC_T2_PIPELINE == 2) {
+                const __amdgpu_buffer_rsrc_t rn = t2_block_rsrc(t2, pos + NS * kTile, off1, NS);
+                load_t2_batch<MT, SB, 0>(tf, rn, lane);
+            }
         }
 #pragma unroll
         for (int i = 0; i < SB; ++i) {
@@ -156,7 +216,7 @@ __device__ __forceinline__ void pair_batches(const int32_t *t2, int64_t pos, int
 
 template <int MT, bool BIGC, int P>
 __device__ __forceinline__ void pair_term(const int32_t *t2, int64_t pos, int64_t off1, int lane,
-                                          const int (&n)[MT], const Roots<MT> &R,
+                                          const int (&n)[MT], const RowSq<MT> &R,
                                           const double2 *__restrict__ gp, const Gather<BIGC> &ldc,
                                           int32_t (&tf)[kSlotBatch<MT>], double &ar, double &ai)
 {
@@ -165,14 +225,16 @@ __device__ __forceinline__ void pair_term(const int32_t *t2, int64_t pos, int64_
     constexpr int NB = (NS + SB - 1) / SB;
     const __amdgpu_buffer_rsrc_t r2 = make_rsrc(t2 + pos, (uint32_t)(NS * kTile * 4));
     const bool valid = K == S ? n[K] >= 2 : (n[K] >= 1 && n[S] >= 1);
-    const double A = valid ? R.s0[K] * (K == S ? R.sm1[K] : R.s0[S]) : 0.0;
+    const double A =
+        valid ? R.template root<0>(K) * (K == S ? R.template root<-1>(K) : R.template root<0>(S))
+              : 0.0;
     // creation amplitudes on m: rq = sqrt(m_q + 1), dq = sqrt(m_q + 2)
     double rq[MT], dq[MT];
 #pragma unroll
     for (int q = 0; q < MT; ++q) {
         const int d = (q == K) + (q == S);
-        rq[q] = d == 0 ? R.sp1[q] : (d == 1 ? R.s0[q] : R.sm1[q]);
-        dq[q] = d == 0 ? R.sp2[q] : (d == 1 ? R.sp1[q] : R.s0[q]);
+        rq[q] = d == 0 ? R.template root<1>(q) : (d == 1 ? R.template root<0>(q) : R.template root<-1>(q));
+        dq[q] = d == 0 ? R.template root<2>(q) : (d == 1 ? R.template root<1>(q) : R.template root<0>(q));
     }
     int32_t tn[SB];
     double br = 0.0, bi = 0.0;
@@ -189,7 +251,7 @@ template <int MT, bool BIGC, int... Ps>
 __device__ __forceinline__ void all_pairs(std::integer_sequence<int, Ps...>,
                                           const uint64_t *pm, const int32_t *t2, int64_t off0,
                                           int64_t off1, int lane, const int (&n)[MT],
-                                          const Roots<MT> &R, const double2 *__restrict__ gp,
+                                          const RowSq<MT> &R, const double2 *__restrict__ gp,
                                           const Gather<BIGC> &ldc, int32_t (&tf)[kSlotBatch<MT>],
                                           double &ar, double &ai)
 {
@@ -209,7 +271,7 @@ __device__ __forceinline__ void all_pairs(std::integer_sequence<int, Ps...>,
 // the single- and double-jump maps; every orbital, pair and slot index is a
 // compile-time constant.  Called by one whole wavefront.
 template <int MT, typename OccT, bool BIGC>
-__device__ __forceinline__ void apply_tile_t2(int64_t tile, int64_t D, int64_t cap,
+__device__ __forceinline__ void apply_tile_t2(int64_t tile, int64_t D, int64_t cap, const double *sq,
                                               const OccT *__restrict__ occ,
                                               const int32_t *__restrict__ t1,
                                               const uint64_t *__restrict__ pmask,
@@ -232,11 +294,12 @@ __device__ __forceinline__ void apply_tile_t2(int64_t tile, int64_t D, int64_t c
     int64_t off0, off1;
     t2_block(t2_off, tile, cap, off0, off1);
     int32_t tf[kSlotBatch<MT>];
-    load_t2_batch<MT, kSlotBatch<MT>, 0>(tf, t2_block_rsrc(t2, off0, off1, M * M), lane);
+    if constexpr (MC_T2_PIPELINE == 2)
+        load_t2_batch<MT, kSlotBatch<MT>, 0>(tf, t2_block_rsrc(t2, off0, off1, M * M), lane);
 
     int n[M];
-    Roots<M> R;
-    load_row<MT, OccT>(occ, tile, M, lane, n, R);
+    RowSq<M> R;
+    load_row<MT, OccT>(occ, tile, lane, n, R, sq);
     const Gather<BIGC> ldc(C, D);
 
     // diagonal one-body part: sum_k h_kk n_k C_g
@@ -281,7 +344,7 @@ __device__ __forceinline__ void apply_tile_t2(int64_t tile, int64_t D, int64_t c
                 if (j >= NS) break;
                 const int k = j / M, l = j % M;
                 if (k == l) continue;
-                const double f = R.s0[k] * R.sp1[l];
+                const double f = R.template root<0>(k) * R.template root<1>(l);
                 const double2 hv = h[j];
                 const double cr = c[i].x * f, ci = c[i].y * f;
                 ar = fma(hv.x, cr, ar);
@@ -305,30 +368,37 @@ __device__ __forceinline__ void apply_tile_t2(int64_t tile, int64_t D, int64_t c
 // intermediate configuration,
 //     T2[g][(k,s)][q*M + l] = T1[T1[g][k][q]][s][l],
 // which holds for every valid removal pair (the intermediate still has a
-// particle in s).  The tile's single-jump rows stay in registers (they also
-// feed the one-body term); the second hop is a gather from rows near g.
+// particle in s).  For q = k the first hop leaves the row unchanged and the
+// target is the single jump T1[g][s][l].  First hops and q = k targets come
+// from the tile's own single-jump block (coalesced, cache-resident); the
+// second hop is a gather from rows near g.
 // ---------------------------------------------------------------------------
 template <int MT, bool BIGC, int P>
 __device__ __forceinline__ void pair_term_chained(int64_t D, const int32_t *__restrict__ t1,
-                                                  int lane, const int (&n)[MT],
-                                                  const Roots<MT> &R,
-                                                  const int32_t (&tr)[MT * MT],
+                                                  __amdgpu_buffer_rsrc_t r1, int lane,
+                                                  const int (&n)[MT], const RowSq<MT> &R,
                                                   const double2 *__restrict__ gp,
-                                                  const Gather<BIGC> &ldc, double &ar,
-                                                  double &ai)
+                                                  const Gather<BIGC> &ldc, double &ar, double &ai)
 {
     constexpr int K = pair_k(MT, P), S = pair_s(MT, P);
     constexpr int NS = MT * MT, SB = kSlotBatch<MT>;
     const bool valid = K == S ? n[K] >= 2 : (n[K] >= 1 && n[S] >= 1);
     if (!__ballot(valid)) return;   // no row of the tile can lose (K, S)
-    const double A = valid ? R.s0[K] * (K == S ? R.sm1[K] : R.s0[S]) : 0.0;
+    const double A =
+        valid ? R.template root<0>(K) * (K == S ? R.template root<-1>(K) : R.template root<0>(S))
+              : 0.0;
     double rq[MT], dq[MT];
 #pragma unroll
     for (int q = 0; q < MT; ++q) {
         const int d = (q == K) + (q == S);
-        rq[q] = d == 0 ? R.sp1[q] : (d == 1 ? R.s0[q] : R.sm1[q]);
-        dq[q] = d == 0 ? R.sp2[q] : (d == 1 ? R.sp1[q] : R.s0[q]);
+        rq[q] = d == 0 ? R.template root<1>(q) : (d == 1 ? R.template root<0>(q) : R.template root<-1>(q));
+        dq[q] = d == 0 ? R.template root<2>(q) : (d == 1 ? R.template root<1>(q) : R.template root<0>(q));
     }
+    // first hops K -> q of this row
+    int32_t fh[MT];
+#pragma unroll
+    for (int q = 0; q < MT; ++q)
+        fh[q] = q == K ? 0 : buf_ld_i32(r1, (uint32_t)(((K * MT + q) * kTile + lane) * 4), 0);
     const double2 *G = gp + P * NS;
     double br = 0.0, bi = 0.0;
 #pragma unroll
@@ -341,10 +411,10 @@ __device__ __forceinline__ void pair_term_chained(int64_t D, const int32_t *__re
             if (j >= NS) break;
             const int q = j / MT, l = j % MT;
             if (q == K) {
-                // first hop k -> k leaves the row unchanged
-                t[i] = valid ? tr[S * MT + l] : -1;
+                const int32_t v = buf_ld_i32(r1, (uint32_t)(((S * MT + l) * kTile + lane) * 4), 0);
+                t[i] = valid ? v : -1;
             } else {
-                const int32_t b = tr[K * MT + q];
+                const int32_t b = fh[q];
                 const bool ok = valid && b >= 0 && b < D;
                 const int64_t bb = ok ? b : 0;
                 const int32_t v = t1[((bb >> 6) * NS + S * MT + l) * kTile + (bb & 63)];
@@ -372,21 +442,107 @@ __device__ __forceinline__ void pair_term_chained(int64_t D, const int32_t *__re
     ai = fma(A, bi, ai);
 }
 
+// The same double jumps for M >= 6 with the removal pairs as a loop: the
+// compile-time fold over M(M+1)/2 pairs of M^2 slots each keeps too many
+// values live at once there.  K and S are wave-uniform loop counters; q and
+// l stay compile-time, so the per-row occupations are picked with selects and
+// the roots come from the block's sqrt table.
+template <int MT, bool BIGC>
+__device__ __forceinline__ void pairs_chained_loop(int64_t D, int64_t g,
+                                                   const int32_t *__restrict__ t1,
+                                                   __amdgpu_buffer_rsrc_t r1, int lane,
+                                                   const int (&n)[MT], const double *sq,
+                                                   const double2 *__restrict__ gp,
+                                                   const Gather<BIGC> &ldc, double &ar, double &ai)
+{
+    constexpr int NS = MT * MT, SB = kSlotBatch<MT>;
+    int P = 0;
+#pragma unroll 1
+    for (int K = 0; K < MT; ++K) {
+#pragma unroll 1
+        for (int S = K; S < MT; ++S, ++P) {
+            int nK = 0, nS = 0;
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                nK = m == K ? n[m] : nK;
+                nS = m == S ? n[m] : nS;
+            }
+            const bool valid = K == S ? nK >= 2 : (nK >= 1 && nS >= 1);
+            if (!__ballot(valid)) continue;
+            const double A = valid ? sq[nK] * (K == S ? sq[nK > 0 ? nK - 1 : 0] : sq[nS]) : 0.0;
+            // first hops K -> q (q = K: the row itself)
+            int32_t b[MT];
+#pragma unroll
+            for (int q = 0; q < MT; ++q) {
+                const int32_t f = buf_ld_i32(r1, (uint32_t)(((K * MT + q) * kTile + lane) * 4), 0);
+                b[q] = q == K ? (int32_t)g : f;
+            }
+            double rq[MT];
+#pragma unroll
+            for (int q = 0; q < MT; ++q) {
+                const int i = n[q] + 1 - (q == K) - (q == S);
+                rq[q] = sq[i > 0 ? i : 0];
+            }
+            const double2 *G = gp + (int64_t)P * NS;
+            double br = 0.0, bi = 0.0;
+#pragma unroll
+            for (int j0 = 0; j0 < NS; j0 += SB) {
+                int32_t t[SB];
+                double2 c[SB];
+#pragma unroll
+                for (int i = 0; i < SB; ++i) {
+                    const int j = j0 + i;
+                    if (j >= NS) break;
+                    const int q = j / MT, l = j % MT;
+                    const int32_t bq = b[q];
+                    const bool ok = valid && bq >= 0 && bq < D;
+                    const int64_t bb = ok ? bq : 0;
+                    const int32_t v = t1[((bb >> 6) * NS + S * MT + l) * kTile + (bb & 63)];
+                    t[i] = ok ? v : -1;
+                }
+#pragma unroll
+                for (int i = 0; i < SB; ++i)
+                    if (j0 + i < NS) c[i] = ldc(t[i]);
+#pragma unroll
+                for (int i = 0; i < SB; ++i) {
+                    const int j = j0 + i;
+                    if (j >= NS) break;
+                    const int q = j / MT, l = j % MT;
+                    double Bv;
+                    if (q == l) {
+                        const int i2 = n[q] + 2 - (q == K) - (q == S);
+                        Bv = rq[q] * sq[i2 > 0 ? i2 : 0];
+                    } else {
+                        Bv = rq[q] * rq[l];
+                    }
+                    const double cr = c[i].x * Bv, ci = c[i].y * Bv;
+                    const double2 Gv = G[j];
+                    br = fma(Gv.x, cr, br);
+                    br = fma(-Gv.y, ci, br);
+                    bi = fma(Gv.x, ci, bi);
+                    bi = fma(Gv.y, cr, bi);
+                }
+            }
+            ar = fma(A, br, ar);
+            ai = fma(A, bi, ai);
+        }
+    }
+}
+
 template <int MT, bool BIGC, int... Ps>
 __device__ __forceinline__ void all_pairs_chained(std::integer_sequence<int, Ps...>, int64_t D,
-                                                  const int32_t *__restrict__ t1, int lane,
-                                                  const int (&n)[MT], const Roots<MT> &R,
-                                                  const int32_t (&tr)[MT * MT],
+                                                  const int32_t *__restrict__ t1,
+                                                  __amdgpu_buffer_rsrc_t r1, int lane,
+                                                  const int (&n)[MT], const RowSq<MT> &R,
                                                   const double2 *__restrict__ gp,
-                                                  const Gather<BIGC> &ldc, double &ar,
-                                                  double &ai)
+                                                  const Gather<BIGC> &ldc, double &ar, double &ai)
 {
-    (pair_term_chained<MT, BIGC, Ps>(D, t1, lane, n, R, tr, gp, ldc, ar, ai), ...);
+    (pair_term_chained<MT, BIGC, Ps>(D, t1, r1, lane, n, R, gp, ldc, ar, ai), ...);
 }
 
 // One 64-row tile of H.C through single jumps only (see above).
 template <int MT, typename OccT, bool BIGC>
-__device__ __forceinline__ void apply_tile_chained(int64_t tile, int64_t D,
+__device__ __forceinline__ void apply_tile_chained(int64_t tile, int64_t D, const double *sq,
                                                    const OccT *__restrict__ occ,
                                                    const int32_t *__restrict__ t1,
                                                    const double2 *__restrict__ h,
@@ -396,20 +552,16 @@ __device__ __forceinline__ void apply_tile_chained(int64_t tile, int64_t D,
 {
     constexpr int M = MT;
     constexpr int P = M * (M + 1) / 2;
+    constexpr int NS = M * M, SB = kSlotBatch<MT>;
     const int lane = threadIdx.x & 63;
     const int64_t g = tile * kTile + lane;
     const bool live = g < D;
     int n[M];
-    Roots<M> R;
-    load_row<MT, OccT>(occ, tile, M, lane, n, R);
+    RowSq<M> R;
+    load_row<MT, OccT>(occ, tile, lane, n, R, sq);
     const Gather<BIGC> ldc(C, D);
-    int32_t tr[M * M];
-    {
-        const __amdgpu_buffer_rsrc_t r1 =
-            make_rsrc(t1 + tile * M * M * kTile, (uint32_t)(M * M * kTile * 4));
-#pragma unroll
-        for (int j = 0; j < M * M; ++j) tr[j] = buf_ld_i32(r1, (uint32_t)((j * kTile + lane) * 4), 0);
-    }
+    const __amdgpu_buffer_rsrc_t r1 =
+        make_rsrc(t1 + tile * NS * kTile, (uint32_t)(NS * kTile * 4));
     const double2 cg = ldc(live ? (int32_t)g : -1);
     double ar, ai;
     {
@@ -423,36 +575,42 @@ __device__ __forceinline__ void apply_tile_chained(int64_t tile, int64_t D,
         ar = dr * cg.x - di * cg.y;
         ai = dr * cg.y + di * cg.x;
     }
-    {
-        constexpr int S1 = M * (M - 1);
-        double2 c[S1 > 0 ? S1 : 1];
-        int j = 0;
+    // single jumps k -> l (k != l), in batches
 #pragma unroll
-        for (int k = 0; k < M; ++k)
+    for (int j0 = 0; j0 < NS; j0 += SB) {
+        int32_t t[SB];
+        double2 c[SB];
 #pragma unroll
-            for (int l = 0; l < M; ++l)
-                if (l != k) c[j++] = ldc(tr[k * M + l]);
-        j = 0;
+        for (int i = 0; i < SB; ++i) {
+            const int j = j0 + i;
+            if (j < NS && j / M != j % M) t[i] = buf_ld_i32(r1, (uint32_t)((j * kTile + lane) * 4), 0);
+        }
 #pragma unroll
-        for (int k = 0; k < M; ++k)
+        for (int i = 0; i < SB; ++i) {
+            const int j = j0 + i;
+            if (j < NS && j / M != j % M) c[i] = ldc(t[i]);
+        }
 #pragma unroll
-            for (int l = 0; l < M; ++l) {
-                if (l == k) continue;
-                const double f = R.s0[k] * R.sp1[l];
-                const double2 hv = h[k * M + l];
-                const double cr = c[j].x * f, ci = c[j].y * f;
-                ++j;
-                ar = fma(hv.x, cr, ar);
-                ar = fma(-hv.y, ci, ar);
-                ai = fma(hv.x, ci, ai);
-                ai = fma(hv.y, cr, ai);
-            }
+        for (int i = 0; i < SB; ++i) {
+            const int j = j0 + i;
+            if (j >= NS) break;
+            const int k = j / M, l = j % M;
+            if (k == l) continue;
+            const double f = R.template root<0>(k) * R.template root<1>(l);
+            const double2 hv = h[j];
+            const double cr = c[i].x * f, ci = c[i].y * f;
+            ar = fma(hv.x, cr, ar);
+            ar = fma(-hv.y, ci, ar);
+            ai = fma(hv.x, ci, ai);
+            ai = fma(hv.y, cr, ai);
+        }
     }
-    all_pairs_chained<MT, BIGC>(std::make_integer_sequence<int, P>{}, D, t1, lane, n, R, tr, gp,
-                                ldc, ar, ai);
+    if constexpr (kLdsRoots<MT>)
+        pairs_chained_loop<MT, BIGC>(D, g, t1, r1, lane, n, sq, gp, ldc, ar, ai);
+    else
+        all_pairs_chained<MT, BIGC>(std::make_integer_sequence<int, P>{}, D, t1, r1, lane, n, R, gp,
+                                    ldc, ar, ai);
     if (live) HC[g] = make_double2(ar, ai);
 }
-
-
 
 }  // namespace mc

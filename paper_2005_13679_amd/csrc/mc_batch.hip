@@ -18,12 +18,18 @@
 #include <vector>
 
 #include "mc_apply.h"
+#include "mc_split.h"
 #include "mc_internal.h"
 
 namespace mc {
 
+// How an instance's tile body runs: paper form through its map or chained,
+// case-split form through its reduced map or chained.
+enum BatchKind : int32_t { kPaperMap = 0, kPaperChain = 1, kSplitMap = 2, kSplitChain = 3 };
+
 struct BatchInst {
     int32_t N, M;
+    int32_t kind, pad;
     int64_t dim, tiles, cap, vec_off;
     const uint8_t *occ;
     const int32_t *t1;
@@ -31,8 +37,16 @@ struct BatchInst {
     const int64_t *t2_off;
     const int32_t *t2;   // null: chain single jumps
     const double2 *h, *g;
-    double2 *hp, *gp;    // staged h' and G'
+    double2 *hp, *gp;    // staged h' and G' (paper form) / gp: case-split constants
 };
+
+// Staged complex constants per instance, enough for either form.
+inline int64_t batch_coef_elems(int M)
+{
+    const int64_t paper = (int64_t)npairs(M) * M * M + (int64_t)M * M;
+    const int64_t split = split_total(M);
+    return paper > split ? paper : split;
+}
 
 struct BatchChunk {
     int32_t inst;
@@ -47,11 +61,12 @@ constexpr int64_t kChunk = 1 << 16;
 struct mc_batch {
     int32_t count;
     int32_t ngroups;
-    int32_t group_M[8];
-    int32_t group_first[8];   // first entry in the sorted instance order
-    int32_t group_count[8];
-    int64_t group_tiles[8];
-    int64_t group_blocks[8];
+    int32_t group_M[32];
+    int32_t group_kind[32];   // BatchKind of the group's instances
+    int32_t group_first[32];  // first entry in the sorted instance order
+    int32_t group_count[32];
+    int64_t group_tiles[32];
+    int64_t group_blocks[32];
     int64_t nchunks;
     int64_t total_len;        // batch-vector length
     int32_t order;
@@ -69,10 +84,14 @@ __global__ void k_batch_prep(const BatchInst *__restrict__ inst)
 {
     const BatchInst I = inst[blockIdx.y];
     const int M = I.M;
+    const int first = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
+    if (I.kind == kSplitMap || I.kind == kSplitChain) {
+        stage_split_constants(M, 0, I.g, I.h, I.gp, first, stride);
+        return;
+    }
     const int P = M * (M + 1) / 2;
     const int total = P * M * M;
-    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total + M * M;
-         idx += gridDim.x * blockDim.x) {
+    for (int idx = first; idx < total + M * M; idx += stride) {
         if (idx >= total) {
             const int e = idx - total;
             I.hp[e] = I.h[e];
@@ -96,16 +115,20 @@ __global__ void k_batch_prep(const BatchInst *__restrict__ inst)
     }
 }
 
-// Persistent H.C over one orbital-count group.  Work item i of the group is
-// tile (i - prefix[j]) of the group's j-th instance; with order 0 wavefront w
-// takes items w, w + W, w + 2W, ... (neighbouring tiles on neighbouring
-// wavefronts), with order 1 a contiguous range of items.
-template <int MT>
+// Persistent H.C over one group (one orbital count and one BatchKind).  Work item i of the group is tile
+// (i - prefix[j]) of the group's j-th instance; with order 0 wavefront w takes
+// items w, w + W, w + 2W, ... (neighbouring tiles on neighbouring wavefronts),
+// with order 1 a contiguous range of items.
+constexpr int kBatchMaxN = 255;
+
+template <int MT, int KIND>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MC_APPLY_WAVES)))
 void k_batch_apply(const BatchInst *__restrict__ inst, const int64_t *__restrict__ prefix,
                    int first, int count, int64_t items, int64_t nblocks, int order,
                    const double2 *__restrict__ Cb, double2 *__restrict__ HCb)
 {
+    __shared__ double sq[kLdsRoots<MT> ? kBatchMaxN + 3 : 1];
+    if constexpr (kLdsRoots<MT>) fill_sqrt_table(sq, kBatchMaxN + 3);
     const int64_t W = nblocks * 4;
     const int64_t w = xcd_block(blockIdx.x, nblocks) * 4 + wave_in_block();
     const int64_t per = (items + W - 1) / W;
@@ -121,11 +144,15 @@ void k_batch_apply(const BatchInst *__restrict__ inst, const int64_t *__restrict
         const int64_t tile = i - prefix[first + j];
         const double2 *C = Cb + I.vec_off;
         double2 *HC = HCb + I.vec_off;
-        if (I.t2)
-            apply_tile_t2<MT, uint8_t, false>(tile, I.dim, I.cap, I.occ, I.t1, I.pmask, I.t2_off,
-                                              I.t2, I.hp, I.gp, C, HC);
+        if constexpr (KIND == kPaperMap)
+            apply_tile_t2<MT, uint8_t, false>(tile, I.dim, I.cap, sq, I.occ, I.t1, I.pmask,
+                                              I.t2_off, I.t2, I.hp, I.gp, C, HC);
+        else if constexpr (KIND == kPaperChain)
+            apply_tile_chained<MT, uint8_t, false>(tile, I.dim, sq, I.occ, I.t1, I.hp, I.gp, C,
+                                                   HC);
         else
-            apply_tile_chained<MT, uint8_t, false>(tile, I.dim, I.occ, I.t1, I.hp, I.gp, C, HC);
+            apply_tile_split<MT, uint8_t, false, KIND == kSplitMap>(
+                tile, I.dim, I.cap, sq, I.occ, I.t1, I.pmask, I.t2_off, I.t2, I.gp, C, HC);
     }
 }
 
@@ -247,7 +274,7 @@ static int plan_layout(int32_t count, const mc_batch_item *items, int64_t *nchun
         if (!t) return MC_EINVAL;
         const int M = t->M;
         nchunks += (t->dim + kChunk - 1) / kChunk;
-        coef += (int64_t)npairs(M) * M * M + (int64_t)M * M;
+        coef += batch_coef_elems(M);
     }
     L->inst = 0;
     L->prefix = align256(L->inst + sizeof(BatchInst) * count);
@@ -303,12 +330,17 @@ int mc_batch_create(int32_t count, const mc_batch_item *items, const mc_batch_sc
     const int order = sched ? sched->order : 0;
     if (order != 0 && order != 1) return MC_EINVAL;
 
-    // instance order: by orbital count, then decreasing dimension
+    // instance order: by orbital count, then kind, then decreasing dimension
+    auto kind_of = [](const mc_tables *t) -> int32_t {
+        const bool split = t->form == MC_FORM_REDUCED, map = t->t2_d != nullptr;
+        return split ? (map ? kSplitMap : kSplitChain) : (map ? kPaperMap : kPaperChain);
+    };
     std::vector<int32_t> sorted(count);
     std::iota(sorted.begin(), sorted.end(), 0);
     std::stable_sort(sorted.begin(), sorted.end(), [&](int a, int b) {
         const mc_tables *x = items[a].tables, *y = items[b].tables;
         if (x->M != y->M) return x->M < y->M;
+        if (kind_of(x) != kind_of(y)) return kind_of(x) < kind_of(y);
         return x->dim > y->dim;
     });
     mc_batch *b = (mc_batch *)calloc(1, sizeof(mc_batch));
@@ -330,6 +362,8 @@ int mc_batch_create(int32_t count, const mc_batch_item *items, const mc_batch_sc
         BatchInst &I = inst[j];
         I.N = t->N;
         I.M = t->M;
+        I.kind = kind_of(t);
+        I.pad = 0;
         I.dim = t->dim;
         I.tiles = t->tiles;
         I.cap = t->t2_d ? t->t2_entries : 0;
@@ -342,12 +376,13 @@ int mc_batch_create(int32_t count, const mc_batch_item *items, const mc_batch_sc
         I.h = (const double2 *)items[i].h_d;
         I.g = (const double2 *)items[i].g_d;
         I.gp = coef + cpos;
-        cpos += (int64_t)npairs(t->M) * t->M * t->M;
-        I.hp = coef + cpos;
-        cpos += (int64_t)t->M * t->M;
+        I.hp = coef + cpos + (int64_t)npairs(t->M) * t->M * t->M;
+        cpos += batch_coef_elems(t->M);
         // group bookkeeping
-        if (b->ngroups == 0 || b->group_M[b->ngroups - 1] != t->M) {
+        if (b->ngroups == 0 || b->group_M[b->ngroups - 1] != t->M ||
+            b->group_kind[b->ngroups - 1] != I.kind) {
             b->group_M[b->ngroups] = t->M;
+            b->group_kind[b->ngroups] = I.kind;
             b->group_first[b->ngroups] = j;
             b->group_count[b->ngroups] = 0;
             b->group_tiles[b->ngroups] = 0;
@@ -437,11 +472,18 @@ int mc_batch_apply_H(const mc_batch *b, const double *C_d, double *HC_d, mc_stre
     hipLaunchKernelGGL(k_batch_prep, dim3(4, b->count), dim3(256), 0, s, b->inst_d);
     for (int gi = 0; gi < b->ngroups; ++gi) {
         const int M = b->group_M[gi];
-        MC_DISPATCH_M(M, if constexpr (MT > 0) hipLaunchKernelGGL(
-                             (k_batch_apply<MT>), dim3(b->group_blocks[gi]), dim3(256), 0, s,
-                             b->inst_d, b->tile_prefix_d, b->group_first[gi], b->group_count[gi],
-                             b->group_tiles[gi], b->group_blocks[gi], b->order,
-                             (const double2 *)C_d, (double2 *)HC_d));
+#define MC_BATCH_LAUNCH(KIND)                                                                   \
+    hipLaunchKernelGGL((k_batch_apply<MT, KIND>), dim3(b->group_blocks[gi]), dim3(256), 0, s,   \
+                       b->inst_d, b->tile_prefix_d, b->group_first[gi], b->group_count[gi],     \
+                       b->group_tiles[gi], b->group_blocks[gi], b->order, (const double2 *)C_d, \
+                       (double2 *)HC_d)
+        switch (b->group_kind[gi]) {
+        case kPaperMap: MC_DISPATCH_M(M, if constexpr (MT > 0) MC_BATCH_LAUNCH(kPaperMap)); break;
+        case kPaperChain: MC_DISPATCH_M(M, if constexpr (MT > 0) MC_BATCH_LAUNCH(kPaperChain)); break;
+        case kSplitMap: MC_DISPATCH_M(M, if constexpr (MT > 0) MC_BATCH_LAUNCH(kSplitMap)); break;
+        default: MC_DISPATCH_M(M, if constexpr (MT > 0) MC_BATCH_LAUNCH(kSplitChain)); break;
+        }
+#undef MC_BATCH_LAUNCH
     }
     return launch_status();
 }

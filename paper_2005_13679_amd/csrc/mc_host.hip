@@ -54,6 +54,7 @@ int check_tables(int32_t N, int32_t M, const mc_tables *t, bool need_t2)
     if (D <= 0 || t->dim != D) return MC_EINVAL;
     if (t->tiles != (D + kTile - 1) / kTile) return MC_EINVAL;
     if (!t->binom_d || !t->occ_d || !t->t1_d || !t->pmask_d || !t->t2_off_d) return MC_EINVAL;
+    if (t->form != MC_FORM_PAPER && t->form != MC_FORM_REDUCED) return MC_EINVAL;
     if (need_t2) {
         if (!t->t2_d || t->t2_required < 0) return MC_EINVAL;
         if (t->t2_entries < t->t2_required) return MC_ENOMEM;
@@ -154,6 +155,7 @@ int mc_tables_size(int32_t N, int32_t M, mc_table_sizes *out)
     out->t2_off_bytes = (tiles + 1) * 8;
     const int64_t pairs_total = N >= 2 ? dim_checked(N - 2, M) : 0;
     out->t2_compact_entries = (int64_t)M * M * npairs(M) * pairs_total;
+    out->t2r_compact_entries = reduced_row_entries(M) * pairs_total;
     return MC_OK;
 }
 

@@ -34,6 +34,30 @@ int launch_status();                   // hipGetLastError -> status
 inline int npairs(int M) { return M * (M + 1) / 2; }
 inline int pair_words(int M) { return (npairs(M) + 63) / 64; }
 inline int occ_width(int N) { return N <= 255 ? 1 : 2; }
+// Slots of removal pair (k, s) in the reduced double-jump map: creation
+// pairs q <= l with q, l outside {k, s}.
+__host__ __device__ constexpr int reduced_slots(int M, int k, int s)
+{
+    return k == s ? M * (M - 1) / 2 : (M - 1) * (M - 2) / 2;
+}
+// Staged constants of the case-split apply (complex entries): DL[M],
+// GI[M(M+1)/2], HS[M*M], GS[M*M*M], GD[reduced slots of all pairs].
+__host__ __device__ constexpr int split_dl_offset(int) { return 0; }
+__host__ __device__ constexpr int split_gi_offset(int M) { return M; }
+__host__ __device__ constexpr int split_hs_offset(int M) { return M + M * (M + 1) / 2; }
+__host__ __device__ constexpr int split_gs_offset(int M) { return split_hs_offset(M) + M * M; }
+__host__ __device__ constexpr int split_gd_offset(int M) { return split_gs_offset(M) + M * M * M; }
+__host__ __device__ constexpr int split_total(int M)
+{
+    return split_gd_offset(M) + M * reduced_slots(M, 0, 0) +
+           (M * (M - 1) / 2) * (M >= 2 ? reduced_slots(M, 0, 1) : 0);
+}
+// Entries of one full row of the reduced map (every pair valid).
+inline int64_t reduced_row_entries(int M)
+{
+    return (int64_t)M * reduced_slots(M, 0, 0) +
+           (int64_t)(M * (M - 1) / 2) * (M >= 2 ? reduced_slots(M, 0, 1) : 0);
+}
 
 // Validates (N, M) ranges; MC_OK or MC_EINVAL.
 int check_nm(int32_t N, int32_t M);

@@ -12,6 +12,7 @@
 #include <utility>
 
 #include "mc_apply.h"
+#include "mc_split.h"
 #include "mc_internal.h"
 
 namespace mc {
@@ -61,32 +62,59 @@ __global__ void k_prep(int M, int adjoint, const double2 *__restrict__ g,
     }
 }
 
-template <int MT, typename OccT, bool BIGC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MC_APPLY_WAVES)))
-void k_apply(int64_t D, int64_t tiles, int64_t nblocks, int64_t cap, const OccT *__restrict__ occ,
-             const int32_t *__restrict__ t1, const uint64_t *__restrict__ pmask,
-             const int64_t *__restrict__ t2_off, const int32_t *__restrict__ t2,
-             const double2 *__restrict__ h, const double2 *__restrict__ gp,
-             const double2 *__restrict__ C, double2 *__restrict__ HC)
+// Staged constants of the case-split apply (layout in mc_split.h).
+__global__ void k_prep_split(int M, int adjoint, const double2 *__restrict__ g,
+                             const double2 *__restrict__ h, double2 *__restrict__ cf)
 {
+    stage_split_constants(M, adjoint, g, h, cf, blockIdx.x * blockDim.x + threadIdx.x,
+                          gridDim.x * blockDim.x);
+}
+
+// H.C in the case-split form (reduced tables); MAP: reduced double-jump map
+// present, else chained single jumps.
+template <int MT, typename OccT, bool BIGC, bool MAP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MC_APPLY_WAVES)))
+void k_apply_split(int N, int64_t D, int64_t tiles, int64_t nblocks, int64_t cap,
+                   const OccT *__restrict__ occ, const int32_t *__restrict__ t1,
+                   const uint64_t *__restrict__ pmask, const int64_t *__restrict__ t2_off,
+                   const int32_t *__restrict__ t2r, const double2 *__restrict__ cf,
+                   const double2 *__restrict__ C, double2 *__restrict__ HC)
+{
+    extern __shared__ double sq[];
+    if constexpr (kLdsRoots<MT>) fill_sqrt_table(sq, N + 3);
     const int64_t tile = xcd_block(blockIdx.x, nblocks) * 4 + wave_in_block();
     if (tile >= tiles) return;
-    apply_tile_t2<MT, OccT, BIGC>(tile, D, cap, occ, t1, pmask, t2_off, t2, h, gp, C, HC);
+    apply_tile_split<MT, OccT, BIGC, MAP>(tile, D, cap, sq, occ, t1, pmask, t2_off, t2r, cf, C, HC);
 }
 
 template <int MT, typename OccT, bool BIGC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MC_APPLY_WAVES)))
-void k_apply_chained(int64_t D, int64_t tiles, int64_t nblocks,
-                                                        const OccT *__restrict__ occ,
-                                                        const int32_t *__restrict__ t1,
-                                                        const double2 *__restrict__ h,
-                                                        const double2 *__restrict__ gp,
-                                                        const double2 *__restrict__ C,
-                                                        double2 *__restrict__ HC)
+void k_apply(int N, int64_t D, int64_t tiles, int64_t nblocks, int64_t cap,
+             const OccT *__restrict__ occ, const int32_t *__restrict__ t1,
+             const uint64_t *__restrict__ pmask, const int64_t *__restrict__ t2_off,
+             const int32_t *__restrict__ t2, const double2 *__restrict__ h,
+             const double2 *__restrict__ gp, const double2 *__restrict__ C,
+             double2 *__restrict__ HC)
 {
+    extern __shared__ double sq[];
+    if constexpr (kLdsRoots<MT>) fill_sqrt_table(sq, N + 3);
     const int64_t tile = xcd_block(blockIdx.x, nblocks) * 4 + wave_in_block();
     if (tile >= tiles) return;
-    apply_tile_chained<MT, OccT, BIGC>(tile, D, occ, t1, h, gp, C, HC);
+    apply_tile_t2<MT, OccT, BIGC>(tile, D, cap, sq, occ, t1, pmask, t2_off, t2, h, gp, C, HC);
+}
+
+template <int MT, typename OccT, bool BIGC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MC_APPLY_WAVES)))
+void k_apply_chained(int N, int64_t D, int64_t tiles, int64_t nblocks,
+                     const OccT *__restrict__ occ, const int32_t *__restrict__ t1,
+                     const double2 *__restrict__ h, const double2 *__restrict__ gp,
+                     const double2 *__restrict__ C, double2 *__restrict__ HC)
+{
+    extern __shared__ double sq[];
+    if constexpr (kLdsRoots<MT>) fill_sqrt_table(sq, N + 3);
+    const int64_t tile = xcd_block(blockIdx.x, nblocks) * 4 + wave_in_block();
+    if (tile >= tiles) return;
+    apply_tile_chained<MT, OccT, BIGC>(tile, D, sq, occ, t1, h, gp, C, HC);
 }
 
 // H.C for any M (run-time orbital loops; the occupations and roots of each
@@ -209,8 +237,14 @@ __global__ __launch_bounds__(256) void k_rho1_generic(int Mrt, int64_t D, int64_
     for (int64_t tile = wave; tile < tiles; tile += nwaves) {
         const int64_t g = tile * kTile + lane;
         int n[MA];
-        Roots<MA> R;
-        load_row<MT, OccT>(occ, tile, M, lane, n, R);
+        double s0[MA], sp1[MA];
+#pragma unroll (kUnroll<MT>)
+        for (int m = 0; m < MA; ++m) {
+            if (MT == 0 && m >= M) break;
+            n[m] = (int)occ[(tile * M + m) * kTile + lane];
+            s0[m] = sqrt((double)n[m]);
+            sp1[m] = sqrt((double)n[m] + 1.0);
+        }
         const double2 cg = ldc(g < D ? (int32_t)g : -1);
         const __amdgpu_buffer_rsrc_t r1 =
             make_rsrc(t1 + tile * M * M * kTile, (uint32_t)(M * M * kTile * 4));
@@ -228,7 +262,7 @@ __global__ __launch_bounds__(256) void k_rho1_generic(int Mrt, int64_t D, int64_
                     const int32_t t =
                         buf_ld_i32(r1, lane * 4, (uint32_t)((k * M + l) * kTile * 4));
                     const double2 c = ldc(t);
-                    const double f = R.s0[k] * R.sp1[l];
+                    const double f = s0[k] * sp1[l];
                     // conj(C_g) * C_t * f
                     vr = (cg.x * c.x + cg.y * c.y) * f;
                     vi = (cg.x * c.y - cg.y * c.x) * f;
@@ -259,12 +293,6 @@ __global__ __launch_bounds__(256) void k_rho1_generic(int Mrt, int64_t D, int64_
 // ---------------------------------------------------------------------------
 constexpr int kRhoChunk = 32;   // slots accumulated per pass
 
-// sqrt(i) for i = 0 .. N+2 into LDS (block-wide)
-__device__ __forceinline__ void fill_sqrt_table(double *tab, int n)
-{
-    for (int i = threadIdx.x; i < n; i += blockDim.x) tab[i] = sqrt((double)i);
-    __syncthreads();
-}
 
 // rho1: elements e = k*M + l, chunk [J0, J0 + CH) of them per pass
 template <int MT, typename OccT, bool BIGC, int J0>
@@ -771,7 +799,13 @@ int mc_workspace_size(int32_t N, int32_t M, int32_t op, size_t *bytes)
     const int64_t tiles = (D + kTile - 1) / kTile;
     const int64_t P = npairs(M);
     switch (op) {
-    case MC_OP_APPLY: *bytes = (size_t)((P * M * M + M * M) * 16); return MC_OK;
+    case MC_OP_APPLY: {
+        // staged constants of either form
+        const int64_t paper = P * M * M + M * M;
+        const int64_t split = M <= 8 ? split_total(M) : 0;
+        *bytes = (size_t)((paper > split ? paper : split) * 16);
+        return MC_OK;
+    }
     case MC_OP_RHO1: *bytes = (size_t)rho_waves(tiles) * M * M * 16; return MC_OK;
     case MC_OP_RHO2: *bytes = (size_t)rho_waves(tiles) * P * M * M * 16; return MC_OK;
     case MC_OP_DOT: *bytes = (size_t)(MC_DOT_BLOCKS + 1) * 16; return MC_OK;
@@ -796,12 +830,47 @@ static int apply_common(int32_t N, int32_t M, const double *h_d, const double *g
     if (ws_bytes < need) return MC_ENOMEM;
     if (M > 8 && (chained || (size_t)5 * M * kTile * 8 > 65536)) return MC_EINVAL;
     hipStream_t s = (hipStream_t)stream;
+    if (t->form == MC_FORM_REDUCED) {
+        if (M > 8) return MC_EINVAL;
+        const size_t sqb = (size_t)(N + 3) * 8;
+        if (sqb > 65536) return MC_EINVAL;
+        double2 *cf = (double2 *)ws_d;
+        hipLaunchKernelGGL(k_prep_split, dim3(4), dim3(256), 0, s, M, adjoint,
+                           (const double2 *)g_d, (const double2 *)h_d, cf);
+        const int64_t nblocks = (t->tiles + 3) / 4;
+        const bool big = D * 16 > (int64_t)0xFFFFFFFFu;
+        bool launched = false;
+        // same instantiation rules as the paper form: 16-bit occupations only
+        // for M <= 5, 64-bit gathers only without a map
+#define MC_SPLIT_LAUNCH(OT, BIG, MAP)                                                          \
+    MC_DISPATCH_M(M, if constexpr (MT > 0 && (MT <= 5 || sizeof(OT) == 1) && !(BIG && MAP)) {   \
+        hipLaunchKernelGGL((k_apply_split<MT, OT, BIG, MAP>), dim3(nblocks), dim3(256),         \
+                           kLdsRoots<MT> ? sqb : 0, s, N, D, t->tiles, nblocks, t->t2_entries,   \
+                           (const OT *)t->occ_d, t->t1_d, t->pmask_d, t->t2_off_d, t->t2_d,     \
+                           (const double2 *)cf, (const double2 *)C_d, (double2 *)HC_d);         \
+        launched = true;                                                                       \
+    })
+        if (chained) {
+            if (occ_width(N) == 1) {
+                if (big) { MC_SPLIT_LAUNCH(uint8_t, true, false); } else { MC_SPLIT_LAUNCH(uint8_t, false, false); }
+            } else {
+                if (big) { MC_SPLIT_LAUNCH(uint16_t, true, false); } else { MC_SPLIT_LAUNCH(uint16_t, false, false); }
+            }
+        } else if (!big) {
+            if (occ_width(N) == 1) { MC_SPLIT_LAUNCH(uint8_t, false, true); } else { MC_SPLIT_LAUNCH(uint16_t, false, true); }
+        }
+#undef MC_SPLIT_LAUNCH
+        if (!launched) return MC_EINVAL;
+        return launch_status();
+    }
     double2 *gp = (double2 *)ws_d;
     double2 *hp = gp + (size_t)npairs(M) * M * M;
     hipLaunchKernelGGL(k_prep, dim3(4), dim3(256), 0, s, M, adjoint, (const double2 *)g_d,
                        (const double2 *)h_d, gp, hp);
     const int64_t nblocks = (t->tiles + 3) / 4;
     const bool big = D * 16 > (int64_t)0xFFFFFFFFu;
+    const size_t sqb = (size_t)(N + 3) * 8;   // sqrt table for M >= 6
+    if (sqb > 65536) return MC_EINVAL;
     // Instantiated combinations: 16-bit occupations only for M <= 5 (M >= 6
     // with N > 255 has D > 2^31), 64-bit gathers (D >= 2^28) only without the
     // double-jump map (a double-jump map of that size cannot fit in HBM).
@@ -809,7 +878,8 @@ static int apply_common(int32_t N, int32_t M, const double *h_d, const double *g
 #define MC_APPLY_LAUNCH(OT, BIG)                                                               \
     if (M <= 8) {                                                                              \
         MC_DISPATCH_M(M, if constexpr (MT > 0 && !BIG && (MT <= 5 || sizeof(OT) == 1)) {        \
-            hipLaunchKernelGGL((k_apply<MT, OT, BIG>), dim3(nblocks), dim3(256), 0, s, D,        \
+            hipLaunchKernelGGL((k_apply<MT, OT, BIG>), dim3(nblocks), dim3(256),                \
+                               kLdsRoots<MT> ? sqb : 0, s, N, D,                               \
                                t->tiles, nblocks, t->t2_entries, (const OT *)t->occ_d, t->t1_d,  \
                                t->pmask_d, t->t2_off_d, t->t2_d, (const double2 *)hp,            \
                                (const double2 *)gp, (const double2 *)C_d, (double2 *)HC_d);     \
@@ -825,7 +895,8 @@ static int apply_common(int32_t N, int32_t M, const double *h_d, const double *g
     }
 #define MC_CHAINED_LAUNCH(OT, BIG)                                                             \
     MC_DISPATCH_M(M, if constexpr (MT > 0 && (MT <= 5 || sizeof(OT) == 1)) {                     \
-        hipLaunchKernelGGL((k_apply_chained<MT, OT, BIG>), dim3(nblocks), dim3(256), 0, s, D,    \
+        hipLaunchKernelGGL((k_apply_chained<MT, OT, BIG>), dim3(nblocks), dim3(256),            \
+                           kLdsRoots<MT> ? sqb : 0, s, N, D,                                     \
                            t->tiles, nblocks, (const OT *)t->occ_d, t->t1_d, (const double2 *)hp, \
                            (const double2 *)gp, (const double2 *)C_d, (double2 *)HC_d);         \
         launched = true;                                                                       \
@@ -910,7 +981,7 @@ int mc_rho2(int32_t N, int32_t M, const mc_tables *t, const double *C_d, double 
     if (st) return st;
     st = check_tables(N, M, t, true);
     if (st) return st;
-    if (!C_d || !rho2_d || !ws_d) return MC_EINVAL;
+    if (t->form != MC_FORM_PAPER || !C_d || !rho2_d || !ws_d) return MC_EINVAL;
     size_t need = 0;
     mc_workspace_size(N, M, MC_OP_RHO2, &need);
     if (ws_bytes < need) return MC_ENOMEM;

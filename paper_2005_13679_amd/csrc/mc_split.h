@@ -1,0 +1,479 @@
+// H.C in the case-split form (tables in the reduced form, M <= 8).
+//
+// The two-body sum of Eq. (Haction) runs over removal pairs {k, s} and
+// creation pairs {q, l}.  Where the two pairs coincide the configuration
+// does not change; where they share one orbital the net effect is a single
+// jump; only disjoint pairs move two particles (the coincident-index cases
+// of the appendix on matrix elements).  Summing the amplitudes per target
+// turns the first two groups into per-row coefficients of C_g and of the
+// single-jump gathers that the one-body term already makes:
+//
+//   coincident:  A_ks B_ks = n_k n_s (k < s),  n_k (n_k - 1) (k = s)
+//   one shared orbital c, net a -> b:  A_{ac} B_{cb} = (n_c - [c = a]) sqrt(n_a (n_b + 1))
+//
+// so the row coefficient is quadratic and the single-jump coefficient linear
+// in the occupations, with constants staged once per call (k_prep_split).
+// The disjoint pairs are gathered from the reduced double-jump map or, with
+// no map, as two chained single jumps.  B_ql of a disjoint pair is taken on
+// the row's own occupations, since q and l are untouched by the removal.
+//
+// Staged constants (complex), g' = staged pair coefficient incl. the 1/2:
+//   DL[k]        h_kk - I_kk
+//   GI[p]        I_ks = g'_{ks,ks} + g'_{ks,sk} (k < s), g'_{kk,kk}
+//   HS[a*M+b]    h_ab - S_aba                      (a != b)
+//   GS[(a*M+b)*M+c]  S_abc = g'_{ac,cb} + g'_{ac,bc} (c != b), g'_{ac,bb}
+//   GD[pair p, slot r]  g'_{ks,ql} + g'_{ks,lq} (q < l), g'_{ks,qq}
+#pragma once
+
+#include <utility>
+
+#include "mc_apply.h"
+
+namespace mc {
+
+// Rank of the creation pair (q, l), q <= l, among the pairs of orbitals
+// outside {K, S}, in lexicographic order (closed form, so that it folds to a
+// constant when its arguments are).
+__host__ __device__ constexpr int reduced_rank(int M, int K, int S, int q, int l)
+{
+    const int E = M - (K == S ? 1 : 2);
+    const int qq = q - (q > K) - (S != K && q > S);
+    const int ll = l - (l > K) - (S != K && l > S);
+    return qq * E - qq * (qq - 1) / 2 + (ll - qq);
+}
+
+// Whether slot (q, l), q <= l, of pair (K, S) is a true double jump.
+__host__ __device__ constexpr bool reduced_slot(int K, int S, int q, int l)
+{
+    return q != K && q != S && l != K && l != S;
+}
+
+// Offset of pair p's constants within GD.
+__host__ __device__ constexpr int reduced_pair_offset(int M, int p)
+{
+    int o = 0;
+    for (int i = 0; i < p; ++i) o += reduced_slots(M, pair_k(M, i), pair_s(M, i));
+    return o;
+}
+
+// Staged constants of the case-split apply from h and g (or their
+// adjoints, g^dagger_ksql = conj(g_lqsk)): entries first, first + stride, ...
+__device__ inline void stage_split_constants(int M, int adjoint, const double2 *__restrict__ g,
+                                             const double2 *__restrict__ h,
+                                             double2 *__restrict__ cf, int first, int stride)
+{
+    auto gat = [&](int k, int s, int q, int l) -> double2 {
+        if (!adjoint) return g[((k * M + s) * M + q) * M + l];
+        const double2 v = g[((l * M + q) * M + s) * M + k];
+        return make_double2(v.x, -v.y);
+    };
+    auto add = [](double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); };
+    auto sub = [](double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); };
+    // g'_{ks,ql} for the unordered removal pair {k, s}
+    auto gpv = [&](int k, int s, int q, int l) -> double2 {
+        const int a = k < s ? k : s, b = k < s ? s : k;
+        double2 v = gat(a, b, q, l);
+        if (a != b) v = add(v, gat(b, a, q, l));
+        return make_double2(0.5 * v.x, 0.5 * v.y);
+    };
+    auto hv = [&](int k, int l) -> double2 {
+        const double2 v = adjoint ? h[l * M + k] : h[k * M + l];
+        return make_double2(v.x, adjoint ? -v.y : v.y);
+    };
+    auto gi = [&](int k, int s) -> double2 {
+        double2 v = gpv(k, s, k, s);
+        if (k != s) v = add(v, gpv(k, s, s, k));
+        return v;
+    };
+    auto gs = [&](int a, int b, int c) -> double2 {
+        return c != b ? add(gpv(a, c, c, b), gpv(a, c, b, c)) : gpv(a, c, b, b);
+    };
+    const int total = split_total(M);
+    for (int idx = first; idx < total; idx += stride) {
+        double2 v = make_double2(0.0, 0.0);
+        if (idx < split_gi_offset(M)) {
+            const int k = idx;
+            v = sub(hv(k, k), gi(k, k));
+        } else if (idx < split_hs_offset(M)) {
+            int p = idx - split_gi_offset(M), k = 0;
+            while (p >= M - k) {
+                p -= M - k;
+                ++k;
+            }
+            v = gi(k, k + p);
+        } else if (idx < split_gs_offset(M)) {
+            const int j = idx - split_hs_offset(M), a = j / M, b = j % M;
+            if (a != b) v = sub(hv(a, b), gs(a, b, a));
+        } else if (idx < split_gd_offset(M)) {
+            const int e = idx - split_gs_offset(M), j = e / M, c = e % M, a = j / M, b = j % M;
+            if (a != b) v = gs(a, b, c);
+        } else {
+            // pair and reduced slot of entry e, both in lexicographic order
+            int e = idx - split_gd_offset(M);
+            int k = 0, s = 0;
+            for (k = 0; k < M; ++k) {
+                for (s = k; s < M; ++s) {
+                    const int nd = reduced_slots(M, k, s);
+                    if (e < nd) break;
+                    e -= nd;
+                }
+                if (s < M) break;
+            }
+            for (int q = 0; q < M; ++q)
+                for (int l = q; l < M; ++l) {
+                    if (q == k || q == s || l == k || l == s) continue;
+                    if (e-- == 0) v = q < l ? add(gpv(k, s, q, l), gpv(k, s, l, q)) : gpv(k, s, q, q);
+                }
+        }
+        cf[idx] = v;
+    }
+}
+
+// Contribution of removal pair P through the reduced map block at `pos`
+// (nd(K, S) * 64 entries): A_KS sum_r GD[P][r] B_r C[t2r slot r].  All
+// slot reads, then all gathers, then the arithmetic (nd <= 10 at M <= 5).
+template <int MT, bool BIGC, int P>
+__device__ __forceinline__ void split_pair_map(const int32_t *t2r, int64_t pos, int lane,
+                                               const int (&n)[MT], const RowSq<MT> &R,
+                                               const double2 *__restrict__ gd,
+                                               const Gather<BIGC> &ldc, double &ar, double &ai)
+{
+    constexpr int K = pair_k(MT, P), S = pair_s(MT, P);
+    constexpr int ND = reduced_slots(MT, K, S);
+    constexpr int CO = reduced_pair_offset(MT, P);
+    const bool valid = K == S ? n[K] >= 2 : (n[K] >= 1 && n[S] >= 1);
+    const double A =
+        valid ? R.template root<0>(K) * (K == S ? R.template root<-1>(K) : R.template root<0>(S))
+              : 0.0;
+    const __amdgpu_buffer_rsrc_t r2 = make_rsrc(t2r + pos, (uint32_t)(ND * kTile * 4));
+    int32_t t[ND];
+    double2 c[ND];
+#pragma unroll
+    for (int r = 0; r < ND; ++r) t[r] = buf_ld_i32(r2, (uint32_t)((r * kTile + lane) * 4), 0);
+#pragma unroll
+    for (int r = 0; r < ND; ++r) c[r] = ldc(t[r]);
+    double br = 0.0, bi = 0.0;
+#pragma unroll
+    for (int j = 0; j < MT * MT; ++j) {
+        const int q = j / MT, l = j % MT;
+        if (l < q || !reduced_slot(K, S, q, l)) continue;
+        const int r = reduced_rank(MT, K, S, q, l);
+        const double Bf = q == l ? R.template root<1>(q) * R.template root<2>(q)
+                                 : R.template root<1>(q) * R.template root<1>(l);
+        const double cr = c[r].x * Bf, ci = c[r].y * Bf;
+        const double2 Gv = gd[CO + r];
+        br = fma(Gv.x, cr, br);
+        br = fma(-Gv.y, ci, br);
+        bi = fma(Gv.x, ci, bi);
+        bi = fma(Gv.y, cr, bi);
+    }
+    ar = fma(A, br, ar);
+    ai = fma(A, bi, ai);
+}
+
+template <int MT, bool BIGC, int... Ps>
+__device__ __forceinline__ void split_pairs_map(std::integer_sequence<int, Ps...>,
+                                                const uint64_t *pm, const int32_t *t2r,
+                                                int64_t off0, int64_t off1, int lane,
+                                                const int (&n)[MT], const RowSq<MT> &R,
+                                                const double2 *__restrict__ gd,
+                                                const Gather<BIGC> &ldc, double &ar, double &ai)
+{
+    int64_t pos = off0;
+    (
+        [&] {
+            constexpr int NSB = reduced_slots(MT, pair_k(MT, Ps), pair_s(MT, Ps)) * kTile;
+            if constexpr (NSB > 0) {
+                if (((pm[Ps >> 6] >> (Ps & 63)) & 1) && pos + NSB <= off1) {
+                    split_pair_map<MT, BIGC, Ps>(t2r, pos, lane, n, R, gd, ldc, ar, ai);
+                    pos += NSB;
+                }
+            }
+        }(),
+        ...);
+}
+
+// The same pair through two chained single jumps: first K -> q from the
+// tile's own single-jump block, then S -> l from the intermediate row.
+template <int MT, bool BIGC, int P>
+__device__ __forceinline__ void split_pair_chain(int64_t D, const int32_t *__restrict__ t1,
+                                                 __amdgpu_buffer_rsrc_t r1, int lane,
+                                                 const int (&n)[MT], const RowSq<MT> &R,
+                                                 const double2 *__restrict__ gd,
+                                                 const Gather<BIGC> &ldc, double &ar, double &ai)
+{
+    constexpr int K = pair_k(MT, P), S = pair_s(MT, P);
+    constexpr int ND = reduced_slots(MT, K, S), NS = MT * MT;
+    constexpr int CO = reduced_pair_offset(MT, P);
+    if constexpr (ND > 0) {
+        const bool valid = K == S ? n[K] >= 2 : (n[K] >= 1 && n[S] >= 1);
+        if (!__ballot(valid)) return;   // no row of the tile can lose (K, S)
+        const double A = valid ? R.template root<0>(K) *
+                                     (K == S ? R.template root<-1>(K) : R.template root<0>(S))
+                               : 0.0;
+        int32_t fh[MT];
+#pragma unroll
+        for (int q = 0; q < MT; ++q)
+            if (q != K && q != S)
+                fh[q] = buf_ld_i32(r1, (uint32_t)(((K * MT + q) * kTile + lane) * 4), 0);
+        int32_t t[ND];
+        double2 c[ND];
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            const int q = j / MT, l = j % MT;
+            if (l < q || !reduced_slot(K, S, q, l)) continue;
+            const int r = reduced_rank(MT, K, S, q, l);
+            const int32_t b = fh[q];
+            const bool ok = valid && b >= 0 && b < D;
+            const int64_t bb = ok ? b : 0;
+            const int32_t v = t1[((bb >> 6) * NS + S * MT + l) * kTile + (bb & 63)];
+            t[r] = ok ? v : -1;
+        }
+#pragma unroll
+        for (int r = 0; r < ND; ++r) c[r] = ldc(t[r]);
+        double br = 0.0, bi = 0.0;
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            const int q = j / MT, l = j % MT;
+            if (l < q || !reduced_slot(K, S, q, l)) continue;
+            const int r = reduced_rank(MT, K, S, q, l);
+            const double Bf = q == l ? R.template root<1>(q) * R.template root<2>(q)
+                                     : R.template root<1>(q) * R.template root<1>(l);
+            const double cr = c[r].x * Bf, ci = c[r].y * Bf;
+            const double2 Gv = gd[CO + r];
+            br = fma(Gv.x, cr, br);
+            br = fma(-Gv.y, ci, br);
+            bi = fma(Gv.x, ci, bi);
+            bi = fma(Gv.y, cr, bi);
+        }
+        ar = fma(A, br, ar);
+        ai = fma(A, bi, ai);
+    }
+}
+
+template <int MT, bool BIGC, int... Ps>
+__device__ __forceinline__ void split_pairs_chain(std::integer_sequence<int, Ps...>, int64_t D,
+                                                  const int32_t *__restrict__ t1,
+                                                  __amdgpu_buffer_rsrc_t r1, int lane,
+                                                  const int (&n)[MT], const RowSq<MT> &R,
+                                                  const double2 *__restrict__ gd,
+                                                  const Gather<BIGC> &ldc, double &ar, double &ai)
+{
+    (split_pair_chain<MT, BIGC, Ps>(D, t1, r1, lane, n, R, gd, ldc, ar, ai), ...);
+}
+
+// M >= 6: the removal pairs as a loop (K, S wave-uniform), creation pairs
+// q <= l compile-time with the excluded ones (sharing an orbital with
+// {K, S}) masked to index -1.  Roots from the block's sqrt table.  MAP
+// selects the reduced map (block at `pos` per present pair) or chaining.
+template <int MT, bool BIGC, bool MAP>
+__device__ __forceinline__ void split_pairs_loop(int64_t D, const int32_t *__restrict__ t1,
+                                                 __amdgpu_buffer_rsrc_t r1, const uint64_t *pm,
+                                                 const int32_t *t2r, int64_t off0, int64_t off1,
+                                                 int lane, const int (&n)[MT], const double *sq,
+                                                 const double2 *__restrict__ gd,
+                                                 const Gather<BIGC> &ldc, double &ar, double &ai)
+{
+    constexpr int NQ = MT * (MT + 1) / 2, NS = MT * MT;
+    constexpr int SB = NQ < MC_SLOT_BATCH ? NQ : MC_SLOT_BATCH;
+    double rq[MT], dq[MT];
+#pragma unroll
+    for (int q = 0; q < MT; ++q) {
+        rq[q] = sq[n[q] + 1];
+        dq[q] = sq[n[q] + 2];
+    }
+    int64_t pos = off0;
+    int P = 0, co = 0;
+#pragma unroll 1
+    for (int K = 0; K < MT; ++K) {
+#pragma unroll 1
+        for (int S = K; S < MT; ++S, ++P) {
+            const int ND = reduced_slots(MT, K, S);
+            const int cbase = co;
+            co += ND;
+            bool present;
+            __amdgpu_buffer_rsrc_t r2;
+            if constexpr (MAP) {
+                present = ((pm[P >> 6] >> (P & 63)) & 1) && ND > 0 &&
+                          pos + (int64_t)ND * kTile <= off1;
+                if (!present) continue;
+                r2 = make_rsrc(t2r + pos, (uint32_t)(ND * kTile * 4));
+                pos += (int64_t)ND * kTile;
+            }
+            int nK = 0, nS = 0;
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                nK = m == K ? n[m] : nK;
+                nS = m == S ? n[m] : nS;
+            }
+            const bool valid = K == S ? nK >= 2 : (nK >= 1 && nS >= 1);
+            if (ND == 0 || !__ballot(valid)) continue;
+            const double A = valid ? sq[nK] * (K == S ? sq[nK > 0 ? nK - 1 : 0] : sq[nS]) : 0.0;
+            int32_t fh[MT];
+            if constexpr (!MAP) {
+#pragma unroll
+                for (int q = 0; q < MT; ++q)
+                    fh[q] = buf_ld_i32(r1, (uint32_t)(((K * MT + q) * kTile + lane) * 4), 0);
+            }
+            double br = 0.0, bi = 0.0;
+#pragma unroll
+            for (int u0 = 0; u0 < NQ; u0 += SB) {
+                int32_t t[SB];
+                double2 c[SB];
+#pragma unroll
+                for (int i = 0; i < SB; ++i) {
+                    // u -> (q, l), q <= l, lexicographic
+                    const int u = u0 + i;
+                    if (u >= NQ) break;
+                    const int q = pair_k(MT, u), l = pair_s(MT, u);
+                    const bool use = reduced_slot(K, S, q, l);
+                    if constexpr (MAP) {
+                        const int r = use ? reduced_rank(MT, K, S, q, l) : 0;
+                        const int32_t v = buf_ld_i32(r2, (uint32_t)((r * kTile + lane) * 4), 0);
+                        t[i] = use ? v : -1;
+                    } else {
+                        const int32_t b = fh[q];
+                        const bool ok = use && valid && b >= 0 && b < D;
+                        const int64_t bb = ok ? b : 0;
+                        const int32_t v = t1[((bb >> 6) * NS + S * MT + l) * kTile + (bb & 63)];
+                        t[i] = ok ? v : -1;
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < SB; ++i)
+                    if (u0 + i < NQ) c[i] = ldc(t[i]);
+#pragma unroll
+                for (int i = 0; i < SB; ++i) {
+                    const int u = u0 + i;
+                    if (u >= NQ) break;
+                    const int q = pair_k(MT, u), l = pair_s(MT, u);
+                    const bool use = reduced_slot(K, S, q, l);
+                    const int r = use ? reduced_rank(MT, K, S, q, l) : 0;
+                    const double Bf = q == l ? rq[q] * dq[q] : rq[q] * rq[l];
+                    const double2 Gv = use ? gd[cbase + r] : make_double2(0.0, 0.0);
+                    const double cr = c[i].x * Bf, ci = c[i].y * Bf;
+                    br = fma(Gv.x, cr, br);
+                    br = fma(-Gv.y, ci, br);
+                    bi = fma(Gv.x, ci, bi);
+                    bi = fma(Gv.y, cr, bi);
+                }
+            }
+            ar = fma(A, br, ar);
+            ai = fma(A, bi, ai);
+        }
+    }
+}
+
+// One 64-row tile of H.C in the case-split form; MAP: true double jumps from
+// the reduced map, else chained.  `cf` holds the staged constants.
+template <int MT, typename OccT, bool BIGC, bool MAP>
+__device__ __forceinline__ void apply_tile_split(int64_t tile, int64_t D, int64_t cap,
+                                                 const double *sq, const OccT *__restrict__ occ,
+                                                 const int32_t *__restrict__ t1,
+                                                 const uint64_t *__restrict__ pmask,
+                                                 const int64_t *__restrict__ t2_off,
+                                                 const int32_t *__restrict__ t2r,
+                                                 const double2 *__restrict__ cf,
+                                                 const double2 *__restrict__ C,
+                                                 double2 *__restrict__ HC)
+{
+    constexpr int M = MT;
+    constexpr int P = M * (M + 1) / 2;
+    constexpr int W = (P + 63) / 64;
+    constexpr int NS = M * M, SB = kSlotBatch<MT>;
+    const int lane = threadIdx.x & 63;
+    const int64_t g = tile * kTile + lane;
+    const bool live = g < D;
+    int n[M];
+    RowSq<M> R;
+    load_row<MT, OccT>(occ, tile, lane, n, R, sq);
+    double x[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) x[m] = (double)n[m];
+    const Gather<BIGC> ldc(C, D);
+    const double2 *DL = cf + split_dl_offset(M);
+    const double2 *GI = cf + split_gi_offset(M);
+    const double2 *HS = cf + split_hs_offset(M);
+    const double2 *GS = cf + split_gs_offset(M);
+    const double2 *GD = cf + split_gd_offset(M);
+
+    // the row's own coefficient (one-body diagonal and coincident pairs)
+    const double2 cg = ldc(live ? (int32_t)g : -1);
+    double ar, ai;
+    {
+        double dr = 0.0, di = 0.0;
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            dr = fma(DL[k].x, x[k], dr);
+            di = fma(DL[k].y, x[k], di);
+        }
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const double w = x[pair_k(M, p)] * x[pair_s(M, p)];
+            dr = fma(GI[p].x, w, dr);
+            di = fma(GI[p].y, w, di);
+        }
+        ar = dr * cg.x - di * cg.y;
+        ai = dr * cg.y + di * cg.x;
+    }
+
+    // single jumps a -> b with coefficient sqrt(n_a (n_b+1)) (HS + sum_c n_c GS)
+    const __amdgpu_buffer_rsrc_t r1 = make_rsrc(t1 + tile * NS * kTile, (uint32_t)(NS * kTile * 4));
+#pragma unroll
+    for (int j0 = 0; j0 < NS; j0 += SB) {
+        int32_t t[SB];
+        double2 c[SB];
+#pragma unroll
+        for (int i = 0; i < SB; ++i) {
+            const int j = j0 + i;
+            if (j < NS && j / M != j % M) t[i] = buf_ld_i32(r1, (uint32_t)((j * kTile + lane) * 4), 0);
+        }
+#pragma unroll
+        for (int i = 0; i < SB; ++i) {
+            const int j = j0 + i;
+            if (j < NS && j / M != j % M) c[i] = ldc(t[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < SB; ++i) {
+            const int j = j0 + i;
+            if (j >= NS) break;
+            const int a = j / M, b = j % M;
+            if (a == b) continue;
+            double er = HS[j].x, ei = HS[j].y;
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                er = fma(GS[j * M + k].x, x[k], er);
+                ei = fma(GS[j * M + k].y, x[k], ei);
+            }
+            const double f = R.template root<0>(a) * R.template root<1>(b);
+            er *= f;
+            ei *= f;
+            ar = fma(er, c[i].x, ar);
+            ar = fma(-ei, c[i].y, ar);
+            ai = fma(er, c[i].y, ai);
+            ai = fma(ei, c[i].x, ai);
+        }
+    }
+
+    // true double jumps
+    if constexpr (MAP) {
+        int64_t off0, off1;
+        t2_block(t2_off, tile, cap, off0, off1);
+        if constexpr (kLdsRoots<MT>)
+            split_pairs_loop<MT, BIGC, true>(D, t1, r1, pmask + tile * W, t2r, off0, off1, lane, n,
+                                             sq, GD, ldc, ar, ai);
+        else
+            split_pairs_map<MT, BIGC>(std::make_integer_sequence<int, P>{}, pmask + tile * W, t2r,
+                                      off0, off1, lane, n, R, GD, ldc, ar, ai);
+    } else {
+        if constexpr (kLdsRoots<MT>)
+            split_pairs_loop<MT, BIGC, false>(D, t1, r1, nullptr, nullptr, 0, 0, lane, n, sq, GD,
+                                              ldc, ar, ai);
+        else
+            split_pairs_chain<MT, BIGC>(std::make_integer_sequence<int, P>{}, D, t1, r1, lane, n, R,
+                                        GD, ldc, ar, ai);
+    }
+    if (live) HC[g] = make_double2(ar, ai);
+}
+
+}  // namespace mc

@@ -41,7 +41,8 @@ __global__ void k_binom(int N, int M, int64_t *__restrict__ binom)
 }
 
 template <int MT, typename OccT>
-__global__ __launch_bounds__(256) void k_build_index(int N, int Mrt, int64_t D, int64_t tiles,
+__global__ __launch_bounds__(256) void k_build_index(int N, int Mrt, int form, int64_t D,
+                                                      int64_t tiles,
                                                       const int64_t *__restrict__ binom,
                                                       OccT *__restrict__ occ,
                                                       int32_t *__restrict__ t1,
@@ -82,14 +83,14 @@ __global__ __launch_bounds__(256) void k_build_index(int N, int Mrt, int64_t D, 
 
     const int W = (M * (M + 1) / 2 + 63) / 64;
     uint64_t word = 0;
-    int64_t count = 0;
+    int64_t slots = 0;
     int p = 0;
     for (int k = 0; k < M; ++k) {
         for (int s = k; s < M; ++s, ++p) {
             const unsigned long long b = __ballot(pair_valid(n, k, s));
             if (b) {
                 word |= (uint64_t)1 << (p & 63);
-                ++count;
+                slots += form == MC_FORM_REDUCED ? reduced_slots(M, k, s) : M * M;
             }
             if ((p & 63) == 63) {
                 if (lane == 0) pmask[tile * W + (p >> 6)] = word;
@@ -98,7 +99,7 @@ __global__ __launch_bounds__(256) void k_build_index(int N, int Mrt, int64_t D, 
         }
     }
     if ((p & 63) != 0 && lane == 0) pmask[tile * W + (p >> 6)] = word;
-    if (lane == 0) t2_len[tile] = count * M * M * kTile;
+    if (lane == 0) t2_len[tile] = slots * kTile;
 }
 
 // Exclusive scan of tiles+1 int64 values in place (the last input is
@@ -198,6 +199,67 @@ __global__ __launch_bounds__(256) void k_build_t2(int N, int Mrt, int64_t tiles,
     }
 }
 
+// Reduced double-jump map (true double jumps only), same tiling as k_build_t2
+// with nd(k, s) slots per present pair.
+template <int MT, typename OccT>
+__global__ __launch_bounds__(256) void k_build_t2r(int N, int Mrt, int64_t tiles,
+                                                    const int64_t *__restrict__ binom,
+                                                    const OccT *__restrict__ occ,
+                                                    const uint64_t *__restrict__ pmask,
+                                                    const int64_t *__restrict__ t2_off,
+                                                    int64_t cap, int32_t *__restrict__ t2)
+{
+    constexpr int MA = MT > 0 ? MT : MC_MAX_M;
+    const int M = MT > 0 ? MT : Mrt;
+    const int lane = threadIdx.x & 63;
+    const int64_t tile = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave_in_block();
+    if (tile >= tiles) return;
+    int n[MA], w[MA];
+#pragma unroll (kUnroll<MT>)
+    for (int m = 0; m < MA; ++m) n[m] = 0;
+    for (int m = 0; m < M; ++m) n[m] = (int)occ[(tile * M + m) * kTile + lane];
+    const int W = (M * (M + 1) / 2 + 63) / 64;
+    // the tile's block must be exactly the sum of its present pairs' slots
+    int64_t want = 0;
+    {
+        int p = 0;
+        for (int k = 0; k < M; ++k)
+            for (int s = k; s < M; ++s, ++p)
+                if ((pmask[tile * W + (p >> 6)] >> (p & 63)) & 1) want += reduced_slots(M, k, s);
+    }
+    int64_t off0, off1;
+    t2_block(t2_off, tile, cap, off0, off1);
+    if (off1 - off0 != want * kTile) return;
+    int32_t *dst = t2 + off0;
+    int p = 0;
+    for (int k = 0; k < M; ++k) {
+        for (int s = k; s < M; ++s, ++p) {
+            const uint64_t word = pmask[tile * W + (p >> 6)];
+            if (!((word >> (p & 63)) & 1)) continue;
+            const bool valid = pair_valid(n, k, s);
+            int r = 0;
+            for (int q = 0; q < M; ++q) {
+                for (int l = q; l < M; ++l) {
+                    if (q == k || q == s || l == k || l == s) continue;
+                    int32_t v = -1;
+                    if (valid) {
+#pragma unroll (kUnroll<MT>)
+                        for (int m = 0; m < MA; ++m) w[m] = n[m];
+                        w[k] -= 1;
+                        w[s] -= 1;
+                        w[q] += 1;
+                        w[l] += 1;
+                        v = (int32_t)dev_hash<MT>(w, M, binom);
+                    }
+                    dst[r * kTile + lane] = v;
+                    ++r;
+                }
+            }
+            dst += (int64_t)r * kTile;
+        }
+    }
+}
+
 template <int MT>
 __global__ void k_hash_batch(int N, int Mrt, const int64_t *__restrict__ binom,
                              const int32_t *__restrict__ occ, int64_t *__restrict__ idx,
@@ -292,12 +354,12 @@ int mc_build_jump_tables(int32_t N, int32_t M, mc_tables *t, mc_stream stream)
     const int64_t blocks = (tiles + 3) / 4;
     if (occ_width(N) == 1) {
         MC_DISPATCH_M(M, hipLaunchKernelGGL((k_build_index<MT, uint8_t>), dim3(blocks), dim3(256),
-                                            0, s, N, M, D, tiles, t->binom_d,
+                                            0, s, N, M, t->form, D, tiles, t->binom_d,
                                             (uint8_t *)t->occ_d, t->t1_d, t->pmask_d,
                                             t->t2_off_d));
     } else {
         MC_DISPATCH_M(M, hipLaunchKernelGGL((k_build_index<MT, uint16_t>), dim3(blocks),
-                                            dim3(256), 0, s, N, M, D, tiles, t->binom_d,
+                                            dim3(256), 0, s, N, M, t->form, D, tiles, t->binom_d,
                                             (uint16_t *)t->occ_d, t->t1_d, t->pmask_d,
                                             t->t2_off_d));
     }
@@ -322,6 +384,20 @@ int mc_build_double_jumps(int32_t N, int32_t M, const mc_tables *t, mc_stream st
     if (st) return st;
     hipStream_t s = (hipStream_t)stream;
     const int64_t blocks = (t->tiles + 3) / 4;
+    if (t->form == MC_FORM_REDUCED) {
+        if (occ_width(N) == 1) {
+            MC_DISPATCH_M(M, hipLaunchKernelGGL((k_build_t2r<MT, uint8_t>), dim3(blocks),
+                                                dim3(256), 0, s, N, M, t->tiles, t->binom_d,
+                                                (const uint8_t *)t->occ_d, t->pmask_d,
+                                                t->t2_off_d, t->t2_entries, t->t2_d));
+        } else {
+            MC_DISPATCH_M(M, hipLaunchKernelGGL((k_build_t2r<MT, uint16_t>), dim3(blocks),
+                                                dim3(256), 0, s, N, M, t->tiles, t->binom_d,
+                                                (const uint16_t *)t->occ_d, t->pmask_d,
+                                                t->t2_off_d, t->t2_entries, t->t2_d));
+        }
+        return launch_status();
+    }
     if (occ_width(N) == 1) {
         MC_DISPATCH_M(M, hipLaunchKernelGGL((k_build_t2<MT, uint8_t>), dim3(blocks), dim3(256), 0,
                                             s, N, M, t->tiles, t->binom_d,
@@ -374,7 +450,7 @@ int mc_t2_lookup(int32_t N, int32_t M, const mc_tables *t, const int64_t *querie
     if (st) return st;
     st = check_tables(N, M, t, true);
     if (st) return st;
-    if (count < 0) return MC_EINVAL;
+    if (t->form != MC_FORM_PAPER || count < 0) return MC_EINVAL;
     if (count == 0) return MC_OK;
     if (!queries_d || !out_d) return MC_EINVAL;
     const int64_t blocks = (count + 255) / 256;

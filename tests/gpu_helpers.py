@@ -26,13 +26,23 @@ def pair_valid(occ, k, s):
     return (occ[:, k] >= 1) & (occ[:, s] >= 1)
 
 
+def pair_slots(M, k, s, form):
+    """Slots of removal pair (k, s) in a double-jump block of the given form."""
+    if form == "paper":
+        return M * M
+    return M * (M - 1) // 2 if k == s else (M - 1) * (M - 2) // 2
+
+
 def tiled_t2_check_and_rows(tables, rows):
     """Reads the tiled double-jump map back and returns, for each requested
-    row, its entries in the paper's per-row layout (valid removal pairs in
-    lexicographic order, M*M slots each).  Also asserts the layout invariants:
+    row, its entries in the per-row layout of the tables' form (valid removal
+    pairs in lexicographic order; M*M slots each in the paper form, the true
+    double jumps in the reduced form).  Also asserts the layout invariants:
     pair mask = union of valid pairs over the tile, offsets consistent with
     the mask, and -1 padding for rows that cannot lose a pair."""
     M, D = tables.M, tables.dim
+    form = tables.form
+    slots = np.array([pair_slots(M, k, s, form) for k, s in pair_list(M)], dtype=np.int64)
     P = M * (M + 1) // 2
     W = (P + 63) // 64
     occ = tables.occupations()
@@ -48,10 +58,11 @@ def tiled_t2_check_and_rows(tables, rows):
     for p, (k, s) in enumerate(pair_list(M)):
         v = pair_valid(occ_pad, k, s).reshape(tables.tiles, TILE).any(axis=1)
         assert np.array_equal(v, bits[:, p]), ("pair mask", p)
-    counts = bits.sum(axis=1).astype(np.int64) * M * M * TILE
+    counts = (bits * slots[None, :]).sum(axis=1).astype(np.int64) * TILE
     assert off[0] == 0 and np.array_equal(np.diff(off), counts), "t2 offsets"
     assert tables.t2_required == off[-1]
-    rank = np.cumsum(bits, axis=1) - 1
+    # start of each pair's block within its tile (in slots)
+    start = np.cumsum(bits * slots[None, :], axis=1) - bits * slots[None, :]
     out = []
     for g in np.asarray(rows, dtype=np.int64):
         tile, lane = divmod(int(g), TILE)
@@ -59,8 +70,8 @@ def tiled_t2_check_and_rows(tables, rows):
         for p, (k, s) in enumerate(pair_list(M)):
             if not bits[tile, p]:
                 continue
-            base = off[tile] + rank[tile, p] * M * M * TILE + lane
-            blk = t2[base + np.arange(M * M) * TILE]
+            base = off[tile] + start[tile, p] * TILE + lane
+            blk = t2[base + np.arange(slots[p]) * TILE]
             n = occ[g]
             ok = (n[k] >= 2) if k == s else (n[k] >= 1 and n[s] >= 1)
             if ok:

@@ -39,10 +39,33 @@ def test_exports_every_declared_symbol(lib):
     assert set(names) == set(_lib.SIGNATURES), "binding and header disagree"
 
 
-def test_struct_layouts_match_header():
+def test_struct_layouts_match_header(tmp_path):
+    """Every field of the ctypes mirrors sits at the offset the C compiler
+    gives it from include/mc.h, and the sizes agree."""
+    import subprocess
     from paper_2005_13679_amd import _lib
-    assert ctypes.sizeof(_lib.CTables) == 8 + 8 * 2 + 8 * 6 + 8 * 2
-    assert ctypes.sizeof(_lib.TableSizes) == 8 * 2 + 4 * 2 + 8 * 6
+    structs = {"mc_tables": _lib.CTables, "mc_table_sizes": _lib.TableSizes,
+               "mc_batch_item": _lib.BatchItem, "mc_batch_schedule": _lib.BatchSchedule}
+    lines = ['#include <stdio.h>', '#include "mc.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)], text=True).split("\n")
+    want = {}
+    for ln in out:
+        if ln:
+            c, f, v = ln.split()
+            want[(c, f)] = int(v)
+    for cname, py in structs.items():
+        assert ctypes.sizeof(py) == want[(cname, "size")], cname
+        for fname, _ in py._fields_:
+            assert getattr(py, fname).offset == want[(cname, fname)], (cname, fname)
 
 
 def test_strerror(lib):

@@ -102,7 +102,8 @@ def test_large_space_sampled_rows(mc, oracle_native):
 
 
 @pytest.mark.parametrize("N,M,seed", [(1, 3, 0), (2, 2, 1), (3, 5, 4), (10, 5, 0), (7, 4, 5), (5, 7, 6),
-                                      (6, 8, 7), (300, 2, 12), (40, 4, 14)])
+                                      (6, 8, 7), (300, 2, 12), (40, 4, 14), (12, 6, 8), (14, 8, 10),
+                                      (20, 7, 11)])
 def test_apply_chained_single_jumps_matches_oracle(mc, oracle_native, N, M, seed):
     """Without the double-jump map the apply chains two single jumps."""
     C, h, g = W.random_instance(N, M, seed)

@@ -10,8 +10,14 @@ from tests.gpu_helpers import rel_inf
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [(8, 3, True), (12, 4, False), (3, 8, True), (10, 5, False), (9, 5, True), (1, 6, False),
-          (20, 3, False), (6, 7, True), (2, 2, True), (15, 6, False)]
+# (N, M, double-jump map, form)
+SHAPES = [(8, 3, True, "paper"), (12, 4, False, "paper"), (3, 8, True, "paper"),
+          (10, 5, False, "paper"), (9, 5, True, "paper"), (1, 6, False, "paper"),
+          (20, 3, False, "paper"), (6, 7, True, "paper"), (2, 2, True, "paper"),
+          (15, 6, False, "paper"), (8, 8, False, "paper"), (5, 7, False, "paper"),
+          (4, 8, True, "paper"), (11, 5, True, "reduced"), (9, 4, False, "reduced"),
+          (6, 8, False, "reduced"), (5, 7, True, "reduced"), (2, 2, True, "reduced"),
+          (3, 1, False, "reduced"), (12, 6, False, "reduced")]
 
 
 def dev(x):
@@ -22,9 +28,9 @@ def dev(x):
 def small_batch(mc):
     from paper_2005_13679_amd.batch import Batch
     insts, host = [], []
-    for i, (N, M, t2) in enumerate(SHAPES):
+    for i, (N, M, t2, form) in enumerate(SHAPES):
         C, h, g = W.random_instance(N, M, 100 + i)
-        tab = mc.build_tables(N, M, double_jumps=t2)
+        tab = mc.build_tables(N, M, double_jumps=t2, form=form)
         insts.append((tab, dev(h), dev(g)))
         host.append((N, M, C, h, g))
     return insts, host

@@ -1,0 +1,104 @@
+"""GPU H.C in the case-split form (reduced tables) vs the oracle: relative
+infinity-norm error <= 1e-12, with the reduced double-jump map and with
+chained single jumps."""
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from tests.gpu_helpers import rel_inf
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+# M = 1..8 (compile-time pair fold for M <= 5, pair loop for M >= 6), 16-bit
+# occupations (N > 255), ragged last tiles, single-tile spaces
+CASES = [(1, 1, 0), (3, 1, 1), (1, 4, 2), (2, 2, 3), (3, 5, 4), (10, 5, 0), (7, 4, 5), (5, 7, 6),
+         (6, 8, 7), (12, 6, 8), (20, 3, 9), (300, 2, 12), (256, 3, 13), (40, 4, 14), (14, 8, 10),
+         (20, 7, 11), (2, 3, 15)]
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+@pytest.mark.parametrize("N,M,seed", CASES)
+def test_split_apply_matches_oracle(mc, oracle_native, N, M, seed):
+    C, h, g = W.random_instance(N, M, seed)
+    ref = oracle_native.apply_h(N, M, h, g, C)
+    tm = mc.build_tables(N, M, form="reduced")
+    tc = mc.build_tables(N, M, form="reduced", double_jumps=False)
+    assert tm.t2 is not None and tc.t2 is None
+    a = mc.apply_H(dev(h), dev(g), dev(C), tm)
+    b = mc.apply_H(dev(h), dev(g), dev(C), tc)
+    assert rel_inf(a.cpu().numpy(), ref) <= TOL
+    # both sources of the true double jumps accumulate in the same order
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("N,M", [(4, 3), (10, 5), (6, 6), (5, 8), (3, 2)])
+def test_split_general_complex_inputs_and_adjoint(mc, oracle_native, N, M):
+    """No symmetry of h or g; the adjoint is H with h -> h^dagger, g -> g^dagger."""
+    rng = np.random.default_rng(N * 10 + M)
+    h = rng.standard_normal((M, M)) + 1j * rng.standard_normal((M, M))
+    g = rng.standard_normal((M,) * 4) + 1j * rng.standard_normal((M,) * 4)
+    D = oracle_native.dim(N, M)
+    C = rng.standard_normal(D) + 1j * rng.standard_normal(D)
+    tab = mc.build_tables(N, M, form="reduced")
+    hc = mc.apply_H(dev(h), dev(g), dev(C), tab).cpu().numpy()
+    assert rel_inf(hc, oracle_native.apply_h(N, M, h, g, C)) <= TOL
+    hd = h.conj().T
+    gd = np.transpose(g, (3, 2, 1, 0)).conj()
+    adj = mc.apply_H_adjoint(dev(h), dev(g), dev(C), tab).cpu().numpy()
+    assert rel_inf(adj, oracle_native.apply_h(N, M, hd, gd, C)) <= TOL
+
+
+def test_split_agrees_with_paper_form(mc):
+    N, M = 30, 5
+    C, h, g = W.random_instance(N, M, 21)
+    paper = mc.apply_H(dev(h), dev(g), dev(C), mc.build_tables(N, M))
+    split = mc.apply_H(dev(h), dev(g), dev(C), mc.build_tables(N, M, form="reduced"))
+    assert rel_inf(split.cpu().numpy(), paper.cpu().numpy()) <= TOL
+
+
+@pytest.mark.parametrize("double_jumps", [True, False])
+def test_split_large_space_sampled_rows(mc, oracle_native, double_jumps):
+    """N = 200, M = 5 (dim 70,058,751), the throughput workload."""
+    N, M = 200, 5
+    C, h, g = W.random_instance(N, M, 2)
+    tab = mc.build_tables(N, M, form="reduced", double_jumps=double_jumps)
+    if double_jumps:
+        # tiled size = entries of the reduced rows plus -1 padding
+        assert tab.t2_required >= int(mc.tables_size(N, M).t2r_compact_entries)
+    Cd = dev(C)
+    hc = mc.apply_H(dev(h), dev(g), Cd, tab)
+    rng = np.random.default_rng(3)
+    D = C.size
+    rows = np.unique(np.concatenate([rng.integers(0, D, 2000), np.arange(128), D - 1 - np.arange(128)]))
+    got = hc[torch.from_numpy(rows).cuda()].cpu().numpy()
+    assert rel_inf(got, oracle_native.apply_h(N, M, h, g, C, rows)) <= TOL
+    e = mc.zdotc(Cd, hc).item()
+    assert abs(e.imag) <= 1e-12 * abs(e.real)
+    del tab, hc, Cd
+    torch.cuda.empty_cache()
+
+
+def test_rho2_needs_paper_map(mc):
+    tab = mc.build_tables(6, 4, form="reduced")
+    C = torch.ones(tab.dim, dtype=torch.complex128, device="cuda")
+    with pytest.raises(mc.MCError):
+        mc.rho2(C, tab)
+    # rho1 reads only the single-jump map
+    assert torch.isfinite(mc.rho1(C, tab).real).all()
+
+
+def test_split_rejects_more_than_eight_orbitals(mc):
+    N, M = 2, 9
+    tab = mc.build_tables(N, M, form="reduced")
+    C = torch.ones(tab.dim, dtype=torch.complex128, device="cuda")
+    h = torch.zeros((M, M), dtype=torch.complex128, device="cuda")
+    g = torch.zeros((M,) * 4, dtype=torch.complex128, device="cuda")
+    with pytest.raises(mc.MCError):
+        mc.apply_H(h, g, C, tab)

@@ -38,6 +38,28 @@ def test_tables_match_oracle(mc, oracle_native, N, M):
     assert sum(len(x) for x in got) == compact
 
 
+@pytest.mark.parametrize("N,M", CASES)
+def test_reduced_tables_match_oracle(mc, oracle_native, N, M):
+    """Reduced double-jump map (true double jumps only) vs the oracle's rows."""
+    tab = mc.build_tables(N, M, form="reduced")
+    torch.cuda.synchronize()
+    rows = np.arange(tab.dim)
+    got = tiled_t2_check_and_rows(tab, rows)
+    off, ent = oracle_native.t2r_rows(N, M)
+    for g in rows:
+        assert np.array_equal(got[g], ent[off[g]:off[g + 1]]), g
+    assert sum(len(x) for x in got) == int(mc.tables_size(N, M).t2r_compact_entries)
+    # the single-jump map does not depend on the form
+    assert np.array_equal(tab.single_jumps(), oracle_native.t1_rows(N, M))
+
+
+def test_lookup_rejects_reduced_form(mc):
+    tab = mc.build_tables(6, 4, form="reduced")
+    q = torch.zeros((1, 5), dtype=torch.int64, device="cuda")
+    with pytest.raises(mc.MCError):
+        mc.t2_lookup(q, tab)
+
+
 @pytest.mark.parametrize("N,M", [(10, 5), (5, 7), (300, 2), (2, 9)])
 def test_lookup_matches_oracle(mc, oracle_native, N, M):
     tab = mc.build_tables(N, M)

@@ -34,6 +34,12 @@ MUTATIONS = {
     # than their lengths, never longer)
     "same_orbital_removal_one_particle": ("            if (k == s) { if (n[k] >= 2) ++p; }",
                                           "            if (k == s) { if (n[k] >= 1) ++p; }"),
+    "reduced_map_wrong_creation_order": (
+        "for (int32_t l = q; l < M; ++l) {\n                        if (q == k",
+        "for (int32_t l = 0; l <= q; ++l) {\n                        if (q == k"),
+    "reduced_map_keeps_shared_orbital": (
+        "                        if (q == k || q == s || l == k || l == s) continue;",
+        "                        if (q == k || l == s) continue;"),
     "unhash_remainder_dropped": ("    if (s > 0) n[0] += (int32_t)s;\n    return 0;",
                                  "    return 0;"),
 }
@@ -112,7 +118,32 @@ def pin_checks(native):
         off, ent = native.t2_rows(N, M)
         assert len(ent) == lens.sum()
 
-    for name, fn in [("worked_example", worked_example), ("bijection", bijection),
+    def reduced_map():
+        N, M = 5, 4
+        occ = native.occ_rows(N, M)
+        off, ent = native.t2r_rows(N, M)
+        per = M * (M * (M - 1) // 2) + (M * (M - 1) // 2) * ((M - 1) * (M - 2) // 2)
+        assert off[-1] == per * cb.nc(N - 2, M)
+        for gam in range(occ.shape[0]):
+            n = occ[gam]
+            want = []
+            for k in range(M):
+                for s in range(k, M):
+                    if not (n[k] >= 2 if k == s else (n[k] >= 1 and n[s] >= 1)):
+                        continue
+                    for q in range(M):
+                        for l in range(q, M):
+                            if q in (k, s) or l in (k, s):
+                                continue
+                            m = n.copy()
+                            m[k] -= 1
+                            m[s] -= 1
+                            m[q] += 1
+                            m[l] += 1
+                            want.append(cb.hash_alg1(list(m)))
+            assert list(ent[off[gam]:off[gam + 1]]) == want
+
+    for name, fn in [("worked_example", worked_example), ("reduced_map", reduced_map), ("bijection", bijection),
                      ("dense_bruteforce", dense_bruteforce), ("single_particle", single_particle),
                      ("pair_counting", pair_counting), ("rho_invariants", rho_invariants),
                      ("jump_counts", jump_counts)]:
@@ -137,6 +168,8 @@ def load_into(native, path):
     lib.orc_t1_rows.argtypes = [i32, i32, p, i64, p]
     lib.orc_t2_row_lengths.argtypes = [i32, i32, p, i64, p]
     lib.orc_t2_rows.argtypes = [i32, i32, p, i64, p, p]
+    lib.orc_t2r_row_lengths.argtypes = [i32, i32, p, i64, p]
+    lib.orc_t2r_rows.argtypes = [i32, i32, p, i64, p, p]
     lib.orc_hash_rows.argtypes = [i32, i32, p, i64, p]
     return lib
 

@@ -102,6 +102,71 @@ def test_double_jump_chains_two_single_jumps(oracle_native):
                     assert ent[off[g] + p * M * M + q * M + l] == b
 
 
+def reduced_slots(M, k, s):
+    return [(q, l) for q in range(M) for l in range(q, M) if q not in (k, s) and l not in (k, s)]
+
+
+@pytest.mark.parametrize("N,M", [(2, 3), (5, 4), (10, 5), (7, 6), (4, 2)])
+def test_reduced_double_jump_definition(oracle_native, N, M):
+    occ = oracle_native.occ_rows(N, M)
+    off, ent = oracle_native.t2r_rows(N, M)
+    for g in range(occ.shape[0]):
+        n = occ[g]
+        row = ent[off[g]:off[g + 1]]
+        want = []
+        for k, s in removal_pairs(n):
+            for q, l in reduced_slots(M, k, s):
+                m = n.copy()
+                m[k] -= 1
+                m[s] -= 1
+                m[q] += 1
+                m[l] += 1
+                want.append(cb.hash_alg1(list(m)))
+        assert list(row) == want
+
+
+@pytest.mark.parametrize("N,M", [(2, 2), (5, 3), (10, 5), (20, 4), (8, 7), (6, 1)])
+def test_reduced_double_jump_total_closed_form(oracle_native, N, M):
+    # (k,k): creation pairs from the other M-1 orbitals, M(M-1)/2 of them;
+    # (k<s): from the other M-2, (M-1)(M-2)/2; each pair valid on N_c(N-2, M) rows
+    lens = oracle_native.t2r_row_lengths(N, M)
+    per = M * (M * (M - 1) // 2) + (M * (M - 1) // 2) * ((M - 1) * (M - 2) // 2)
+    assert lens.sum() == per * cb.nc(N - 2, M)
+
+
+def test_case_split_covers_the_full_map(oracle_native):
+    # every slot of the paper's map is the row itself ({q,l} = {k,s}), a
+    # single jump (one shared orbital) or an entry of the reduced map
+    N, M = 7, 5
+    occ = oracle_native.occ_rows(N, M)
+    t1 = oracle_native.t1_rows(N, M)
+    off, ent = oracle_native.t2_rows(N, M)
+    roff, rent = oracle_native.t2r_rows(N, M)
+    for g in range(occ.shape[0]):
+        red = {}
+        pos = roff[g]
+        for p, (k, s) in enumerate(removal_pairs(occ[g])):
+            for q, l in reduced_slots(M, k, s):
+                red[(k, s, q, l)] = rent[pos]
+                pos += 1
+        for p, (k, s) in enumerate(removal_pairs(occ[g])):
+            for q in range(M):
+                for l in range(M):
+                    v = ent[off[g] + p * M * M + q * M + l]
+                    rem, add = [k, s], [q, l]
+                    for x in (q, l):
+                        if x in rem:
+                            rem.remove(x)
+                            add.remove(x)
+                    if not rem:
+                        assert v == g
+                    elif len(rem) == 1:
+                        assert v == t1[g, rem[0], add[0]]
+                    else:
+                        assert v == red[(k, s, min(q, l), max(q, l))]
+        assert pos == roff[g + 1]
+
+
 def test_table_ii_memory_fits(oracle_native):
     fit = golden("memory_fit.json")
     M = fit["M"]
