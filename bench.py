@@ -4,7 +4,9 @@
 
 A step is one H.C apply (Eq. Haction) through the jump maps on the workload
 N = 200 bosons, M = 5 orbitals (dim 70,058,751), complex128 coefficients;
-inputs and tables are resident in HBM before timing starts.  Prints one JSON
+inputs and tables are resident in HBM before timing starts.  The timed path
+is the case-split sum over the reduced double-jump map by default
+(--path), the other paths are timed beside it.  Prints one JSON
 line with applies/s, the HBM roofline of the apply kernel (algorithmic bytes
 per apply / mean kernel time from HIP events on the launch stream) and the
 CPU oracle timed on a bounded sample of rows on this host.
@@ -32,17 +34,40 @@ WORKLOADS = {
 }
 
 
-def algorithmic_bytes(N: int, M: int) -> dict:
-    """Bytes the table-driven apply must move, each structure once: dense
-    single-jump map (M^2 D int32), compact double-jump rows (M^2 * M(M+1)/2 *
-    N_c(N-2, M) int32), per-row offsets (D+1 int64), occupations (M D uint8),
-    coefficients in and out (16 D each)."""
+# How the apply runs: (table form, double-jump map present)
+PATHS = {
+    "reduced_map": ("reduced", True),      # case-split sum, reduced double-jump map
+    "reduced_chained": ("reduced", False),  # case-split sum, true double jumps chained
+    "paper_map": ("paper", True),          # the paper's sum and double-jump map
+    "paper_chained": ("paper", False),     # the paper's sum, every slot chained
+}
+# dominant kernel of each path (the one the roofline and profiles refer to)
+KERNELS = {
+    "reduced_map": "k_apply_split<5, uint8, false, MAP=true>",
+    "reduced_chained": "k_apply_split<5, uint8, false, MAP=false>",
+    "paper_map": "k_apply<5, uint8, false>",
+    "paper_chained": "k_apply_chained<5, uint8, false>",
+}
+
+
+def algorithmic_bytes(N: int, M: int, path: str = "reduced_map") -> dict:
+    """Bytes one apply must move, each structure once: dense single-jump map
+    (M^2 D int32), the double-jump rows of the path's form (paper: M^2 slots
+    per valid removal pair, M^2 * M(M+1)/2 * N_c(N-2, M) entries; reduced: the
+    true double jumps, [M * M(M-1)/2 + M(M-1)/2 * (M-1)(M-2)/2] * N_c(N-2, M)
+    entries; none when chained), per-row offsets (D+1 int64, with a map),
+    occupations (M D uint8), coefficients in and out (16 D each)."""
+    form, has_map = PATHS[path]
     D = math.comb(N + M - 1, N)
-    t2 = M * M * (M * (M + 1) // 2) * (math.comb(N - 2 + M - 1, N - 2) if N >= 2 else 0)
+    nc2 = math.comb(N - 2 + M - 1, N - 2) if N >= 2 else 0
+    if form == "paper":
+        per_row = M * M * (M * (M + 1) // 2)
+    else:
+        per_row = M * (M * (M - 1) // 2) + (M * (M - 1) // 2) * ((M - 1) * (M - 2) // 2)
     parts = {
         "t1": 4 * M * M * D,
-        "t2": 4 * t2,
-        "offsets": 8 * (D + 1),
+        "t2": 4 * per_row * nc2 if has_map else 0,
+        "offsets": 8 * (D + 1) if has_map else 0,
         "occupations": M * D * (1 if N <= 255 else 2),
         "coefficients_in": 16 * D,
         "coefficients_out": 16 * D,
@@ -53,16 +78,16 @@ def algorithmic_bytes(N: int, M: int) -> dict:
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("mc_ops.hip", "mc_internal.h"):
+    for f in ("mc_ops.hip", "mc_internal.h", "mc_apply.h", "mc_split.h"):
         with open(os.path.join(ROOT, "paper_2005_13679_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(N: int, M: int):
+def measured_traffic(N: int, M: int, path_name: str):
     """HBM bytes per apply from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", f"k_apply_N{N}_M{M}_counters.json")
+    path = os.path.join(ROOT, "profiles", f"{path_name}_N{N}_M{M}_counters.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -154,11 +179,11 @@ def batched_leg(dev, steps: int = 50) -> dict:
     from paper_2005_13679_amd.batch import Batch, BatchedLanczos, choose_double_jumps, plain_lanczos
     import workloads as W
     draws = W.batch_draws(64, 4)
-    use_t2 = choose_double_jumps(draws, budget_bytes=40e9)
+    use_t2 = choose_double_jumps(draws, budget_bytes=40e9, form="reduced")
     insts = []
     for i, ((N, M), t2) in enumerate(zip(draws, use_t2)):
         _, h, g = W.random_instance(1, M, 1000 + i)
-        tab = mc.build_tables(N, M, dev, double_jumps=t2)
+        tab = mc.build_tables(N, M, dev, double_jumps=t2, form="reduced")
         insts.append((tab, torch.from_numpy(h).to(dev), torch.from_numpy(g).to(dev)))
     total_dim = sum(t.dim for t, _, _ in insts)
     print(f"[bench] batched: {len(insts)} instances, total dim {total_dim}; autotuning",
@@ -195,7 +220,7 @@ def batched_leg(dev, steps: int = 50) -> dict:
         if k > 0:
             worst = max(worst, float(np.max(np.abs(a_p[:k] - a_b[:k, i]) / np.maximum(1.0, np.abs(a_p[:k])))))
     t_plain = time.perf_counter() - t0
-    out = {"instances": len(insts), "total_dim": int(total_dim),
+    out = {"instances": len(insts), "total_dim": int(total_dim), "table_form": "reduced",
            "with_double_jump_map": int(sum(use_t2)), "steps": steps,
            "schedule": tuned["schedule"], "schedule_cached": tuned["cached"],
            "batched_apply_ms": apply_ms,
@@ -214,10 +239,12 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="large_random", choices=sorted(WORKLOADS))
+    ap.add_argument("--path", default="reduced_map", choices=sorted(PATHS),
+                    help="table form and double-jump source of the timed apply")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--extras", action="store_true", help="also time rho1/rho2 passes")
     ap.add_argument("--quick", action="store_true",
-                    help="skip the autograd and batched comparison legs")
+                    help="skip the other apply paths and the autograd and batched legs")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="run one elementwise copy of this size first (HBM counter scale)")
     args = ap.parse_args(argv)
@@ -237,8 +264,9 @@ def main(argv=None):
     print(f"[bench] workload {args.workload} N={N} M={M}: drawing inputs", file=sys.stderr, flush=True)
     C, h, g = W.random_instance(N, M, seed)
     D = C.size
+    form, has_map = PATHS[args.path]
     t0 = time.perf_counter()
-    tab = mc.build_tables(N, M, dev)
+    tab = mc.build_tables(N, M, dev, double_jumps=has_map, form=form)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     print(f"[bench] tables built in {build_s:.2f} s ({sum(tab.nbytes().values()) / 1e9:.2f} GB)",
@@ -268,11 +296,11 @@ def main(argv=None):
     end.record(stream)
     torch.cuda.synchronize()
     ms = start.elapsed_time(end) / args.steps
-    print(f"[bench] {args.steps} applies: {ms:.3f} ms each", file=sys.stderr, flush=True)
+    print(f"[bench] {args.steps} applies ({args.path}): {ms:.3f} ms each", file=sys.stderr, flush=True)
 
-    B = algorithmic_bytes(N, M)
+    B = algorithmic_bytes(N, M, args.path)
     achieved = B["total"] / (ms * 1e-3) / 1e9
-    traffic = measured_traffic(N, M)
+    traffic = measured_traffic(N, M, args.path)
     out = {
         "metric": "H.C applies/s (N=200, M=5, complex128) with HBM GB/s",
         "value": 1e3 / ms,
@@ -288,8 +316,10 @@ def main(argv=None):
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: N={N} bosons, M={M} orbitals, dim {D}, "
                                "complex128 C, random Hermitian h, symmetric g",
-                   "N": N, "M": M, "dim": D, "parallelism": "single GPU"},
+                   "N": N, "M": M, "dim": D, "path": args.path, "table_form": form,
+                   "double_jump_map": has_map, "parallelism": "single GPU"},
         "roofline": {
+            "kernel": KERNELS[args.path],
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
@@ -318,6 +348,24 @@ def main(argv=None):
     if not args.quick:
         del tab
         torch.cuda.empty_cache()
+        others = {}
+        for name, (f2, m2) in PATHS.items():
+            if name == args.path:
+                continue
+            print(f"[bench] path {name}", file=sys.stderr, flush=True)
+            t2 = mc.build_tables(N, M, dev, double_jumps=m2, form=f2)
+            for _ in range(2):
+                mc.apply_H(hd, gd, Cd, t2, out=HC)
+            ms2 = _median_ms(lambda: [mc.apply_H(hd, gd, Cd, t2, out=HC) for _ in range(5)], 3,
+                             stream) / 5
+            B2 = algorithmic_bytes(N, M, name)["total"]
+            others[name] = {"ms_per_apply": ms2, "applies_per_s": 1e3 / ms2,
+                            "algorithmic_bytes": B2, "GB_per_s": B2 / (ms2 * 1e-3) / 1e9,
+                            "frac_of_hbm_peak": B2 / (ms2 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                            "table_bytes": sum(t2.nbytes().values()), "kernel": KERNELS[name]}
+            del t2
+            torch.cuda.empty_cache()
+        out["other_paths"] = others
         print("[bench] autograd leg (N=50, M=6)", file=sys.stderr, flush=True)
         out["autograd_vs_plain"] = autograd_leg(dev)
         print("[bench] batched leg (64 instances, 50 Lanczos steps)", file=sys.stderr, flush=True)

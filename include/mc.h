@@ -298,7 +298,10 @@ typedef struct mc_batch_schedule {
     int32_t blocks_per_cu;   /* persistent grid per group: blocks_per_cu x CUs blocks of
                                 256 threads (0 = 2) */
     int32_t order;           /* 0: wavefront w takes work items w, w+W, ...; 1: each
-                                wavefront takes a contiguous range of items */
+                                wavefront takes a contiguous range of items; 2: each
+                                XCD takes a contiguous share of the items (in
+                                proportion to its blocks) and its wavefronts
+                                interleave within it, as a plain launch does */
     int32_t reserved[2];
 } mc_batch_schedule;
 

@@ -17,8 +17,8 @@ import torch
 
 from .batch import Batch
 
-DEFAULT = {"blocks_per_cu": 2, "order": 0}
-CANDIDATES = [{"blocks_per_cu": b, "order": o} for b in (1, 2, 4, 8) for o in (0, 1)]
+DEFAULT = {"blocks_per_cu": 2, "order": 2}
+CANDIDATES = [{"blocks_per_cu": b, "order": o} for b in (1, 2, 4, 8) for o in (0, 1, 2)]
 
 
 def default_cache_path() -> str:

@@ -78,7 +78,7 @@ class Batch:
         sched = L.BatchSchedule()
         schedule = dict(schedule or {})
         sched.blocks_per_cu = int(schedule.get("blocks_per_cu", 2))
-        sched.order = int(schedule.get("order", 0))
+        sched.order = int(schedule.get("order", 2))
         self.schedule = {"blocks_per_cu": sched.blocks_per_cu, "order": sched.order}
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):

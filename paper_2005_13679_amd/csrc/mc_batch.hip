@@ -115,10 +115,12 @@ __global__ void k_batch_prep(const BatchInst *__restrict__ inst)
     }
 }
 
-// Persistent H.C over one group (one orbital count and one BatchKind).  Work item i of the group is tile
-// (i - prefix[j]) of the group's j-th instance; with order 0 wavefront w takes
-// items w, w + W, w + 2W, ... (neighbouring tiles on neighbouring wavefronts),
-// with order 1 a contiguous range of items.
+// Persistent H.C over one group (one orbital count and one BatchKind).
+// Work item i of the group is tile (i - prefix[j]) of the group's j-th
+// instance; with order 0 wavefront w takes items w, w + W, w + 2W, ...
+// (neighbouring tiles on neighbouring wavefronts), with order 1 a contiguous
+// range of items, with order 2 each XCD a contiguous share of the items,
+// interleaved over its wavefronts.
 constexpr int kBatchMaxN = 255;
 
 template <int MT, int KIND>
@@ -131,10 +133,27 @@ void k_batch_apply(const BatchInst *__restrict__ inst, const int64_t *__restrict
     if constexpr (kLdsRoots<MT>) fill_sqrt_table(sq, kBatchMaxN + 3);
     const int64_t W = nblocks * 4;
     const int64_t w = xcd_block(blockIdx.x, nblocks) * 4 + wave_in_block();
-    const int64_t per = (items + W - 1) / W;
-    const int64_t i0 = order == 0 ? w : w * per;
-    const int64_t step = order == 0 ? W : 1;
-    const int64_t iend = order == 0 ? items : (i0 + per < items ? i0 + per : items);
+    int64_t i0, step, iend;
+    if (order == 2) {
+        // blocks go to XCD b % 8; this XCD's blocks own items [ib, ie)
+        const int64_t xcd = blockIdx.x & 7, local = blockIdx.x >> 3;
+        const int64_t bper = nblocks >> 3, brem = nblocks & 7;
+        const int64_t nbx = bper + (xcd < brem ? 1 : 0);
+        const int64_t fb = xcd * bper + (xcd < brem ? xcd : brem);
+        const int64_t ib = items * fb / nblocks, ie = items * (fb + nbx) / nblocks;
+        i0 = ib + local * 4 + wave_in_block();
+        step = nbx * 4;
+        iend = ie;
+    } else if (order == 1) {
+        const int64_t per = (items + W - 1) / W;
+        i0 = w * per;
+        step = 1;
+        iend = i0 + per < items ? i0 + per : items;
+    } else {
+        i0 = w;
+        step = W;
+        iend = items;
+    }
     int j = 0;
     for (int64_t i = i0; i < iend; i += step) {
         // instance of item i (prefix is non-decreasing; items are visited in
@@ -328,7 +347,7 @@ int mc_batch_create(int32_t count, const mc_batch_item *items, const mc_batch_sc
     if (plan_bytes < L.total) return MC_ENOMEM;
     const int bpc = sched && sched->blocks_per_cu > 0 ? sched->blocks_per_cu : 2;
     const int order = sched ? sched->order : 0;
-    if (order != 0 && order != 1) return MC_EINVAL;
+    if (order < 0 || order > 2) return MC_EINVAL;
 
     // instance order: by orbital count, then kind, then decreasing dimension
     auto kind_of = [](const mc_tables *t) -> int32_t {

@@ -31,6 +31,18 @@
 
 namespace mc {
 
+// A wave-uniform true that the compiler cannot see through.  Branching on
+// it puts each batch of a long straight-line stream into a basic block of its
+// own; within one huge block the instruction scheduler issues every load of
+// the stream first and keeps all gathered values live (hundreds of spilled
+// registers), across blocks it cannot move them.
+__device__ __forceinline__ bool opaque_true()
+{
+    int v;
+    asm volatile("s_mov_b32 %0, 1" : "=s"(v));
+    return v != 0;
+}
+
 // Rank of the creation pair (q, l), q <= l, among the pairs of orbitals
 // outside {K, S}, in lexicographic order (closed form, so that it folds to a
 // constant when its arguments are).
@@ -318,6 +330,7 @@ __device__ __forceinline__ void split_pairs_loop(int64_t D, const int32_t *__res
             double br = 0.0, bi = 0.0;
 #pragma unroll
             for (int u0 = 0; u0 < NQ; u0 += SB) {
+                if (!opaque_true()) continue;   // one basic block per batch
                 int32_t t[SB];
                 double2 c[SB];
 #pragma unroll
@@ -361,6 +374,180 @@ __device__ __forceinline__ void split_pairs_loop(int64_t D, const int32_t *__res
             ar = fma(A, br, ar);
             ai = fma(A, bi, ai);
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tiles whose pair mask has every pair (nearly all tiles of large spaces):
+// the tile's single jumps and reduced-map blocks form one stream of
+// U = M(M-1) + sum_p nd(p) slots with a compile-time layout, processed in
+// batches of MC_FLAT_BATCH slots; the next batch's index loads are issued
+// while the current batch's gathers are in flight.  Same arithmetic, in the
+// same order, as the per-pair path.
+// ---------------------------------------------------------------------------
+#ifndef MC_FLAT_BATCH
+#define MC_FLAT_BATCH 16
+#endif
+
+template <int MT>
+struct FlatTile {
+    static constexpr int NSING = MT * (MT - 1);
+    static constexpr int NDBL =
+        MT * reduced_slots(MT, 0, 0) + (MT * (MT - 1) / 2) * (MT >= 2 ? reduced_slots(MT, 0, 1) : 0);
+    static constexpr int U = NSING + NDBL;
+    static constexpr int SB = U < MC_FLAT_BATCH ? U : MC_FLAT_BATCH;
+    static constexpr int NB = (U + SB - 1) / SB;
+};
+
+// double slot e (pair-major) -> pair and slot within the pair
+__host__ __device__ constexpr int flat_pair(int M, int e)
+{
+    for (int p = 0; p < M * (M + 1) / 2; ++p) {
+        const int nd = reduced_slots(M, pair_k(M, p), pair_s(M, p));
+        if (e < nd) return p;
+        e -= nd;
+    }
+    return -1;
+}
+__host__ __device__ constexpr int flat_slot(int M, int e)
+{
+    for (int p = 0; p < M * (M + 1) / 2; ++p) {
+        const int nd = reduced_slots(M, pair_k(M, p), pair_s(M, p));
+        if (e < nd) return e;
+        e -= nd;
+    }
+    return -1;
+}
+// r-th creation pair (q, l) outside {K, S}: q (which = 0) or l (which = 1)
+__host__ __device__ constexpr int reduced_ql(int M, int K, int S, int r, int which)
+{
+    for (int q = 0; q < M; ++q)
+        for (int l = q; l < M; ++l) {
+            if (!reduced_slot(K, S, q, l)) continue;
+            if (r-- == 0) return which ? l : q;
+        }
+    return -1;
+}
+
+template <int MT, int U>
+__device__ __forceinline__ int32_t flat_load(__amdgpu_buffer_rsrc_t r1, __amdgpu_buffer_rsrc_t r2,
+                                             int lane)
+{
+    constexpr int NSING = FlatTile<MT>::NSING;
+    if constexpr (U < NSING) {
+        constexpr int a = U / (MT - 1), bb = U % (MT - 1), b = bb + (bb >= a);
+        return buf_ld_i32(r1, (uint32_t)(((a * MT + b) * kTile + lane) * 4), 0);
+    } else {
+        return buf_ld_i32(r2, (uint32_t)(((U - NSING) * kTile + lane) * 4), 0);
+    }
+}
+
+template <int MT, int U>
+__device__ __forceinline__ void flat_fma(const double2 &c, const int (&n)[MT], const RowSq<MT> &R,
+                                         const double (&x)[MT], const double2 *__restrict__ HS,
+                                         const double2 *__restrict__ GS,
+                                         const double2 *__restrict__ GD, double &br, double &bi,
+                                         double &ar, double &ai)
+{
+    constexpr int NSING = FlatTile<MT>::NSING;
+    if constexpr (U < NSING) {
+        constexpr int a = U / (MT - 1), bb = U % (MT - 1), b = bb + (bb >= a), j = a * MT + b;
+        double er = HS[j].x, ei = HS[j].y;
+#pragma unroll
+        for (int k = 0; k < MT; ++k) {
+            er = fma(GS[j * MT + k].x, x[k], er);
+            ei = fma(GS[j * MT + k].y, x[k], ei);
+        }
+        const double f = R.template root<0>(a) * R.template root<1>(b);
+        er *= f;
+        ei *= f;
+        ar = fma(er, c.x, ar);
+        ar = fma(-ei, c.y, ar);
+        ai = fma(er, c.y, ai);
+        ai = fma(ei, c.x, ai);
+    } else {
+        constexpr int e = U - NSING;
+        constexpr int P = flat_pair(MT, e), r = flat_slot(MT, e);
+        constexpr int K = pair_k(MT, P), S = pair_s(MT, P);
+        constexpr int q = reduced_ql(MT, K, S, r, 0), l = reduced_ql(MT, K, S, r, 1);
+        const double Bf = q == l ? R.template root<1>(q) * R.template root<2>(q)
+                                 : R.template root<1>(q) * R.template root<1>(l);
+        const double cr = c.x * Bf, ci = c.y * Bf;
+        const double2 Gv = GD[e];
+        br = fma(Gv.x, cr, br);
+        br = fma(-Gv.y, ci, br);
+        bi = fma(Gv.x, ci, bi);
+        bi = fma(Gv.y, cr, bi);
+        if constexpr (r == reduced_slots(MT, K, S) - 1) {
+            // last slot of the pair: weight by A_KS as the per-pair path does
+            const bool valid = K == S ? n[K] >= 2 : (n[K] >= 1 && n[S] >= 1);
+            const double A = valid ? R.template root<0>(K) *
+                                         (K == S ? R.template root<-1>(K) : R.template root<0>(S))
+                                   : 0.0;
+            ar = fma(A, br, ar);
+            ai = fma(A, bi, ai);
+            br = 0.0;
+            bi = 0.0;
+        }
+    }
+}
+
+template <int MT, int U0, int... Is>
+__device__ __forceinline__ void flat_loads(std::integer_sequence<int, Is...>,
+                                           int32_t (&t)[FlatTile<MT>::SB],
+                                           __amdgpu_buffer_rsrc_t r1, __amdgpu_buffer_rsrc_t r2,
+                                           int lane)
+{
+    ((U0 + Is < FlatTile<MT>::U ? (void)(t[Is] = flat_load<MT, U0 + Is>(r1, r2, lane)) : (void)0),
+     ...);
+}
+
+template <int MT, int U0, int... Is>
+__device__ __forceinline__ void flat_fmas(std::integer_sequence<int, Is...>,
+                                          const double2 (&c)[FlatTile<MT>::SB], const int (&n)[MT],
+                                          const RowSq<MT> &R, const double (&x)[MT],
+                                          const double2 *__restrict__ HS,
+                                          const double2 *__restrict__ GS,
+                                          const double2 *__restrict__ GD, double &br, double &bi,
+                                          double &ar, double &ai)
+{
+    (
+        [&] {
+            if constexpr (U0 + Is < FlatTile<MT>::U)
+                flat_fma<MT, U0 + Is>(c[Is], n, R, x, HS, GS, GD, br, bi, ar, ai);
+        }(),
+        ...);
+}
+
+// batch B: gathers for the indices in `cur`, then the next batch's index
+// loads into `nxt`, then the arithmetic of batch B
+template <int MT, bool BIGC, int B>
+__device__ __forceinline__ void flat_batches(int32_t (&cur)[FlatTile<MT>::SB],
+                                             int32_t (&nxt)[FlatTile<MT>::SB],
+                                             __amdgpu_buffer_rsrc_t r1, __amdgpu_buffer_rsrc_t r2,
+                                             int lane, const int (&n)[MT], const RowSq<MT> &R,
+                                             const double (&x)[MT], const double2 *__restrict__ HS,
+                                             const double2 *__restrict__ GS,
+                                             const double2 *__restrict__ GD,
+                                             const Gather<BIGC> &ldc, double &br, double &bi,
+                                             double &ar, double &ai)
+{
+    constexpr int SB = FlatTile<MT>::SB, NB = FlatTile<MT>::NB, U = FlatTile<MT>::U;
+    if constexpr (B < NB) {
+        // each batch in a basic block of its own (see opaque_true)
+        if (opaque_true()) {
+            double2 c[SB];
+#pragma unroll
+            for (int i = 0; i < SB; ++i)
+                if (B * SB + i < U) c[i] = ldc(cur[i]);
+            if constexpr (B + 1 < NB)
+                flat_loads<MT, (B + 1) * SB>(std::make_integer_sequence<int, SB>{}, nxt, r1, r2,
+                                             lane);
+            flat_fmas<MT, B * SB>(std::make_integer_sequence<int, SB>{}, c, n, R, x, HS, GS, GD, br,
+                                  bi, ar, ai);
+        }
+        flat_batches<MT, BIGC, B + 1>(nxt, cur, r1, r2, lane, n, R, x, HS, GS, GD, ldc, br, bi, ar,
+                                      ai);
     }
 }
 
@@ -417,8 +604,31 @@ __device__ __forceinline__ void apply_tile_split(int64_t tile, int64_t D, int64_
         ai = dr * cg.y + di * cg.x;
     }
 
-    // single jumps a -> b with coefficient sqrt(n_a (n_b+1)) (HS + sum_c n_c GS)
     const __amdgpu_buffer_rsrc_t r1 = make_rsrc(t1 + tile * NS * kTile, (uint32_t)(NS * kTile * 4));
+    if constexpr (MAP && !kLdsRoots<MT> && FlatTile<MT>::NDBL > 0) {
+        // every pair present and the block exactly the full size: one stream
+        int64_t off0, off1;
+        t2_block(t2_off, tile, cap, off0, off1);
+        bool full = off1 - off0 == (int64_t)FlatTile<MT>::NDBL * kTile;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const int bits = P - 64 * w < 64 ? P - 64 * w : 64;
+            const uint64_t want = bits == 64 ? ~(uint64_t)0 : (((uint64_t)1 << bits) - 1);
+            full = full && pmask[tile * W + w] == want;
+        }
+        if (full) {
+            const __amdgpu_buffer_rsrc_t r2 =
+                make_rsrc(t2r + off0, (uint32_t)(FlatTile<MT>::NDBL * kTile * 4));
+            int32_t ta[FlatTile<MT>::SB], tb[FlatTile<MT>::SB];
+            flat_loads<MT, 0>(std::make_integer_sequence<int, FlatTile<MT>::SB>{}, ta, r1, r2, lane);
+            double br = 0.0, bi = 0.0;
+            flat_batches<MT, BIGC, 0>(ta, tb, r1, r2, lane, n, R, x, HS, GS, GD, ldc, br, bi, ar, ai);
+            if (live) HC[g] = make_double2(ar, ai);
+            return;
+        }
+    }
+
+    // single jumps a -> b with coefficient sqrt(n_a (n_b+1)) (HS + sum_c n_c GS)
 #pragma unroll
     for (int j0 = 0; j0 < NS; j0 += SB) {
         int32_t t[SB];
