@@ -287,7 +287,9 @@ int mc_zaxpby(int64_t n, const double *a_d, const double *x_d, const double *b_d
  *
  * Every batch call only enqueues kernels on `stream` (no host
  * synchronisation, no memset), so sequences of calls can be captured into a
- * HIP graph and replayed.
+ * HIP graph and replayed.  A batch's plan holds staged coefficients and work
+ * counters: applies of one batch that overlap in time (other streams) race;
+ * calls on one stream are ordered.
  */
 typedef struct mc_batch_item {
     const mc_tables *tables;     /* host pointer to built tables of the instance */
@@ -301,8 +303,14 @@ typedef struct mc_batch_schedule {
                                 wavefront takes a contiguous range of items; 2: each
                                 XCD takes a contiguous share of the items (in
                                 proportion to its blocks) and its wavefronts
-                                interleave within it, as a plain launch does */
-    int32_t reserved[2];
+                                interleave within it; 3: wavefronts take 8 items at
+                                a time from a per-group counter in the plan (zeroed
+                                by a kernel at the start of each apply) */
+    int32_t solo_tiles;      /* > 0: an instance of at least this many 64-row tiles
+                                gets a launch of its own (one wavefront per tile, like
+                                mc_apply_H) instead of joining its group's persistent
+                                kernel; 0: every instance joins its group */
+    int32_t reserved;
 } mc_batch_schedule;
 
 typedef struct mc_batch mc_batch;   /* opaque host handle */

@@ -113,7 +113,8 @@ class BatchItem(ctypes.Structure):
 
 
 class BatchSchedule(ctypes.Structure):
-    _fields_ = [("blocks_per_cu", c_i32), ("order", c_i32), ("reserved", c_i32 * 2)]
+    _fields_ = [("blocks_per_cu", c_i32), ("order", c_i32), ("solo_tiles", c_i32),
+                ("reserved", c_i32)]
 
 
 SIGNATURES.update({

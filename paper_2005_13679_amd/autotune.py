@@ -1,7 +1,8 @@
 """Schedule autotuner for batched H.C.
 
 Times one batched apply for each candidate schedule (persistent grid size per
-orbital-count group and work order) on the actual batch and keeps the fastest.
+group, work order, and the size from which an instance gets a launch of its
+own) on the actual batch and keeps the fastest.
 Results are cached in a JSON file keyed by the batch signature (instance
 shapes, which instances use a double-jump map, device name).  Set
 MC_AUTOTUNE=0 to skip tuning and use the default schedule.
@@ -17,8 +18,11 @@ import torch
 
 from .batch import Batch
 
-DEFAULT = {"blocks_per_cu": 2, "order": 2}
-CANDIDATES = [{"blocks_per_cu": b, "order": o} for b in (1, 2, 4, 8) for o in (0, 1, 2)]
+DEFAULT = {"blocks_per_cu": 2, "order": 3, "solo_tiles": 16384}
+# persistent grid size x work order x size from which an instance gets a grid
+# of its own (0: never)
+CANDIDATES = [{"blocks_per_cu": b, "order": o, "solo_tiles": t}
+              for b in (1, 2, 4) for o in (0, 2, 3) for t in (0, 16384)]
 
 
 def default_cache_path() -> str:

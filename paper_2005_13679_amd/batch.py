@@ -78,8 +78,10 @@ class Batch:
         sched = L.BatchSchedule()
         schedule = dict(schedule or {})
         sched.blocks_per_cu = int(schedule.get("blocks_per_cu", 2))
-        sched.order = int(schedule.get("order", 2))
-        self.schedule = {"blocks_per_cu": sched.blocks_per_cu, "order": sched.order}
+        sched.order = int(schedule.get("order", 3))
+        sched.solo_tiles = int(schedule.get("solo_tiles", 16384))
+        self.schedule = {"blocks_per_cu": sched.blocks_per_cu, "order": sched.order,
+                         "solo_tiles": sched.solo_tiles}
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             L.check(lib.mc_batch_create(n, items, ctypes.byref(sched), api._ptr(self.plan),

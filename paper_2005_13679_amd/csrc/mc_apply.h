@@ -53,8 +53,11 @@ struct Gather {
 // For M <= 5 the four tables live in registers; for M >= 6 (where they would
 // cost 8M VGPRs) only the occupations do and the roots come from an LDS table
 // of sqrt(i), i = 0 .. N+2, filled once per block.
+#ifndef MC_LDS_ROOTS_FROM
+#define MC_LDS_ROOTS_FROM 6
+#endif
 template <int MT>
-constexpr bool kLdsRoots = MT >= 6;
+constexpr bool kLdsRoots = MT >= MC_LDS_ROOTS_FROM;
 
 template <int MT, bool LDS = kLdsRoots<MT>>
 struct RowSq;

@@ -38,7 +38,12 @@ struct BatchInst {
     const int32_t *t2;   // null: chain single jumps
     const double2 *h, *g;
     double2 *hp, *gp;    // staged h' and G' (paper form) / gp: case-split constants
+    int64_t hp_off, gp_off;  // the same, as offsets into the plan's coefficient region
 };
+
+// Pointers read from a descriptor are generic (flat loads); the staged
+// constants are therefore reached through the __restrict__ coefficient-region
+// kernel argument, which keeps their loads scalar.
 
 // Staged complex constants per instance, enough for either form.
 inline int64_t batch_coef_elems(int M)
@@ -55,6 +60,16 @@ struct BatchChunk {
 };
 
 constexpr int64_t kChunk = 1 << 16;
+constexpr int kMaxGroups = 32;   // 8 orbital counts x 4 kinds
+constexpr int kGrab = 8;         // tiles a wavefront takes per counter increment (order 3)
+
+// An instance launched on a grid of its own.
+struct SoloLaunch {
+    int32_t j;      // sorted position (index into the plan's descriptors)
+    int32_t M, kind;
+    int32_t pad;
+    int64_t tiles;
+};
 
 }  // namespace mc
 
@@ -76,12 +91,17 @@ struct mc_batch {
     double2 *partials_d;      // [nchunks]
     int32_t *sorted_d;        // [count] sorted position -> caller index
     int32_t *pos_d;           // [count] caller index -> sorted position
+    uint32_t *counters_d;     // [kMaxGroups] work counters of order 3, zeroed per apply
+    double2 *coef_d;          // staged coefficients of all instances
+    int32_t nsolo;            // instances launched on grids of their own
+    mc::SoloLaunch *solo;     // [nsolo] (host)
 };
 
 namespace mc {
 
-__global__ void k_batch_prep(const BatchInst *__restrict__ inst)
+__global__ void k_batch_prep(const BatchInst *__restrict__ inst, uint32_t *__restrict__ counters)
 {
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < kMaxGroups) counters[threadIdx.x] = 0;
     const BatchInst I = inst[blockIdx.y];
     const int M = I.M;
     const int first = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
@@ -115,22 +135,70 @@ __global__ void k_batch_prep(const BatchInst *__restrict__ inst)
     }
 }
 
+// One tile of one instance, in the instance's kind.
+template <int MT, int KIND>
+__device__ __forceinline__ void batch_tile(const BatchInst &I, int64_t tile, const double *sq,
+                                           const double2 *__restrict__ coef,
+                                           const double2 *__restrict__ Cb,
+                                           double2 *__restrict__ HCb)
+{
+    const double2 *C = Cb + I.vec_off;
+    double2 *HC = HCb + I.vec_off;
+    const uint8_t *occ = I.occ;
+    const int32_t *t1 = I.t1;
+    const uint64_t *pmask = I.pmask;
+    const int64_t *t2_off = I.t2_off;
+    const int32_t *t2 = I.t2;
+    const double2 *gp = coef + I.gp_off, *hp = coef + I.hp_off;
+    if constexpr (KIND == kPaperMap)
+        apply_tile_t2<MT, uint8_t, false>(tile, I.dim, I.cap, sq, occ, t1, pmask, t2_off, t2, hp,
+                                          gp, C, HC);
+    else if constexpr (KIND == kPaperChain)
+        apply_tile_chained<MT, uint8_t, false>(tile, I.dim, sq, occ, t1, hp, gp, C, HC);
+    else
+        apply_tile_split<MT, uint8_t, false, KIND == kSplitMap>(tile, I.dim, I.cap, sq, occ, t1,
+                                                                pmask, t2_off, t2, gp, C, HC);
+}
+
 // Persistent H.C over one group (one orbital count and one BatchKind).
 // Work item i of the group is tile (i - prefix[j]) of the group's j-th
 // instance; with order 0 wavefront w takes items w, w + W, w + 2W, ...
 // (neighbouring tiles on neighbouring wavefronts), with order 1 a contiguous
 // range of items, with order 2 each XCD a contiguous share of the items,
-// interleaved over its wavefronts.
+// interleaved over its wavefronts; with order 3 wavefronts take kGrab items
+// at a time from a per-group counter (dynamic balance, like a plain launch).
 constexpr int kBatchMaxN = 255;
 
 template <int MT, int KIND>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MC_APPLY_WAVES)))
 void k_batch_apply(const BatchInst *__restrict__ inst, const int64_t *__restrict__ prefix,
                    int first, int count, int64_t items, int64_t nblocks, int order,
+                   uint32_t *__restrict__ counter, const double2 *__restrict__ coef,
                    const double2 *__restrict__ Cb, double2 *__restrict__ HCb)
 {
     __shared__ double sq[kLdsRoots<MT> ? kBatchMaxN + 3 : 1];
     if constexpr (kLdsRoots<MT>) fill_sqrt_table(sq, kBatchMaxN + 3);
+    auto tile_body = [&](int64_t i, int &j) __attribute__((always_inline)) {
+        // instance of item i (prefix is non-decreasing; a wavefront visits
+        // items in increasing order, so the search resumes where it stopped)
+        while (j + 1 < count && prefix[first + j + 1] <= i) ++j;
+        const BatchInst I = inst[first + j];
+        batch_tile<MT, KIND>(I, i - prefix[first + j], sq, coef, Cb, HCb);
+    };
+    int j = 0;
+    if (order == 3) {
+        // dynamic: take kGrab items at a time from the group's counter (a
+        // vector atomic from lane 0; the count is zeroed by k_batch_prep)
+        for (;;) {
+            uint32_t base = 0;
+            if ((threadIdx.x & 63) == 0) base = atomicAdd(counter, (uint32_t)kGrab);
+            base = __builtin_amdgcn_readfirstlane(base);
+            if ((int64_t)base >= items) break;
+            const int64_t end = (int64_t)base + kGrab < items ? (int64_t)base + kGrab : items;
+            for (int64_t i = base; i < end; ++i) tile_body(i, j);
+        }
+        return;
+    }
     const int64_t W = nblocks * 4;
     const int64_t w = xcd_block(blockIdx.x, nblocks) * 4 + wave_in_block();
     int64_t i0, step, iend;
@@ -154,25 +222,23 @@ void k_batch_apply(const BatchInst *__restrict__ inst, const int64_t *__restrict
         step = W;
         iend = items;
     }
-    int j = 0;
-    for (int64_t i = i0; i < iend; i += step) {
-        // instance of item i (prefix is non-decreasing; items are visited in
-        // increasing order so the search resumes where it stopped)
-        while (j + 1 < count && prefix[first + j + 1] <= i) ++j;
-        const BatchInst I = inst[first + j];
-        const int64_t tile = i - prefix[first + j];
-        const double2 *C = Cb + I.vec_off;
-        double2 *HC = HCb + I.vec_off;
-        if constexpr (KIND == kPaperMap)
-            apply_tile_t2<MT, uint8_t, false>(tile, I.dim, I.cap, sq, I.occ, I.t1, I.pmask,
-                                              I.t2_off, I.t2, I.hp, I.gp, C, HC);
-        else if constexpr (KIND == kPaperChain)
-            apply_tile_chained<MT, uint8_t, false>(tile, I.dim, sq, I.occ, I.t1, I.hp, I.gp, C,
-                                                   HC);
-        else
-            apply_tile_split<MT, uint8_t, false, KIND == kSplitMap>(
-                tile, I.dim, I.cap, sq, I.occ, I.t1, I.pmask, I.t2_off, I.t2, I.gp, C, HC);
-    }
+    for (int64_t i = i0; i < iend; i += step) tile_body(i, j);
+}
+
+// One large instance on a grid of its own: one wavefront per tile, blocks
+// remapped per XCD as in the plain apply.
+template <int MT, int KIND>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MC_APPLY_WAVES)))
+void k_batch_solo(const BatchInst *__restrict__ ip, int64_t nblocks,
+                  const double2 *__restrict__ coef, const double2 *__restrict__ Cb,
+                  double2 *__restrict__ HCb)
+{
+    __shared__ double sq[kLdsRoots<MT> ? kBatchMaxN + 3 : 1];
+    if constexpr (kLdsRoots<MT>) fill_sqrt_table(sq, kBatchMaxN + 3);
+    const BatchInst I = *ip;
+    const int64_t tile = xcd_block(blockIdx.x, nblocks) * 4 + wave_in_block();
+    if (tile >= I.tiles) return;
+    batch_tile<MT, KIND>(I, tile, sq, coef, Cb, HCb);
 }
 
 // Segmented conj(x).y: chunk partials, then per-instance sums in chunk order.
@@ -281,7 +347,7 @@ __global__ __launch_bounds__(256) void k_seg_scale(const BatchChunk *__restrict_
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct PlanLayout {
-    size_t inst, prefix, chunks, partials, sorted, pos, coef, total;
+    size_t inst, prefix, chunks, partials, sorted, pos, counters, coef, total;
 };
 
 static int plan_layout(int32_t count, const mc_batch_item *items, int64_t *nchunks_out,
@@ -301,7 +367,8 @@ static int plan_layout(int32_t count, const mc_batch_item *items, int64_t *nchun
     L->partials = align256(L->chunks + sizeof(BatchChunk) * nchunks);
     L->sorted = align256(L->partials + sizeof(double2) * nchunks);
     L->pos = align256(L->sorted + sizeof(int32_t) * count);
-    L->coef = align256(L->pos + sizeof(int32_t) * count);
+    L->counters = align256(L->pos + sizeof(int32_t) * count);
+    L->coef = align256(L->counters + sizeof(uint32_t) * kMaxGroups);
     L->total = align256(L->coef + sizeof(double2) * coef);
     *nchunks_out = nchunks;
     *coef_elems_out = coef;
@@ -347,7 +414,7 @@ int mc_batch_create(int32_t count, const mc_batch_item *items, const mc_batch_sc
     if (plan_bytes < L.total) return MC_ENOMEM;
     const int bpc = sched && sched->blocks_per_cu > 0 ? sched->blocks_per_cu : 2;
     const int order = sched ? sched->order : 0;
-    if (order < 0 || order > 2) return MC_EINVAL;
+    if (order < 0 || order > 3) return MC_EINVAL;
 
     // instance order: by orbital count, then kind, then decreasing dimension
     auto kind_of = [](const mc_tables *t) -> int32_t {
@@ -364,6 +431,12 @@ int mc_batch_create(int32_t count, const mc_batch_item *items, const mc_batch_sc
     });
     mc_batch *b = (mc_batch *)calloc(1, sizeof(mc_batch));
     if (!b) return MC_ENOMEM;
+    b->solo = (SoloLaunch *)calloc((size_t)count, sizeof(SoloLaunch));
+    if (!b->solo) {
+        free(b);
+        return MC_ENOMEM;
+    }
+    const int64_t solo_min = sched && sched->solo_tiles > 0 ? sched->solo_tiles : 0;
     b->count = count;
     b->order = order;
     std::vector<int32_t> pos(count);
@@ -396,7 +469,20 @@ int mc_batch_create(int32_t count, const mc_batch_item *items, const mc_batch_sc
         I.g = (const double2 *)items[i].g_d;
         I.gp = coef + cpos;
         I.hp = coef + cpos + (int64_t)npairs(t->M) * t->M * t->M;
+        I.gp_off = cpos;
+        I.hp_off = cpos + (int64_t)npairs(t->M) * t->M * t->M;
         cpos += batch_coef_elems(t->M);
+        // a large instance gets a launch of its own; the rest join groups
+        if (solo_min > 0 && t->tiles >= solo_min) {
+            SoloLaunch &L1 = b->solo[b->nsolo++];
+            L1.j = j;
+            L1.M = t->M;
+            L1.kind = I.kind;
+            L1.pad = 0;
+            L1.tiles = t->tiles;
+            prefix[j] = 0;
+            continue;
+        }
         // group bookkeeping
         if (b->ngroups == 0 || b->group_M[b->ngroups - 1] != t->M ||
             b->group_kind[b->ngroups - 1] != I.kind) {
@@ -452,6 +538,8 @@ int mc_batch_create(int32_t count, const mc_batch_item *items, const mc_batch_sc
     b->partials_d = (double2 *)(base + L.partials);
     b->sorted_d = (int32_t *)(base + L.sorted);
     b->pos_d = (int32_t *)(base + L.pos);
+    b->counters_d = (uint32_t *)(base + L.counters);
+    b->coef_d = (double2 *)(base + L.coef);
     hipStream_t s = (hipStream_t)stream;
     st = set_hip_error(hipMemcpyAsync(b->inst_d, inst.data(), sizeof(BatchInst) * count,
                                       hipMemcpyHostToDevice, s));
@@ -468,6 +556,7 @@ int mc_batch_create(int32_t count, const mc_batch_item *items, const mc_batch_sc
     // host staging vectors go out of scope: wait for the copies
     if (!st) st = set_hip_error(hipStreamSynchronize(s));
     if (st) {
+        free(b->solo);
         free(b);
         return st;
     }
@@ -477,6 +566,7 @@ int mc_batch_create(int32_t count, const mc_batch_item *items, const mc_batch_sc
 
 int mc_batch_destroy(mc_batch *b)
 {
+    if (b) free(b->solo);
     free(b);
     return MC_OK;
 }
@@ -488,14 +578,30 @@ int mc_batch_apply_H(const mc_batch *b, const double *C_d, double *HC_d, mc_stre
     if (!b || !C_d || !HC_d) return MC_EINVAL;
     if (overlaps(C_d, (size_t)b->total_len * 16, HC_d, (size_t)b->total_len * 16)) return MC_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_batch_prep, dim3(4, b->count), dim3(256), 0, s, b->inst_d);
+    hipLaunchKernelGGL(k_batch_prep, dim3(4, b->count), dim3(256), 0, s, b->inst_d, b->counters_d);
+    for (int k = 0; k < b->nsolo; ++k) {
+        const int j = b->solo[k].j;
+        const int M = b->solo[k].M;
+        const int64_t nblocks = (b->solo[k].tiles + 3) / 4;
+#define MC_SOLO_LAUNCH(KIND)                                                                    \
+    hipLaunchKernelGGL((k_batch_solo<MT, KIND>), dim3(nblocks), dim3(256), 0, s, b->inst_d + j,  \
+                       nblocks, (const double2 *)b->coef_d, (const double2 *)C_d,                 \
+                       (double2 *)HC_d)
+        switch (b->solo[k].kind) {
+        case kPaperMap: MC_DISPATCH_M(M, if constexpr (MT > 0) MC_SOLO_LAUNCH(kPaperMap)); break;
+        case kPaperChain: MC_DISPATCH_M(M, if constexpr (MT > 0) MC_SOLO_LAUNCH(kPaperChain)); break;
+        case kSplitMap: MC_DISPATCH_M(M, if constexpr (MT > 0) MC_SOLO_LAUNCH(kSplitMap)); break;
+        default: MC_DISPATCH_M(M, if constexpr (MT > 0) MC_SOLO_LAUNCH(kSplitChain)); break;
+        }
+#undef MC_SOLO_LAUNCH
+    }
     for (int gi = 0; gi < b->ngroups; ++gi) {
         const int M = b->group_M[gi];
 #define MC_BATCH_LAUNCH(KIND)                                                                   \
     hipLaunchKernelGGL((k_batch_apply<MT, KIND>), dim3(b->group_blocks[gi]), dim3(256), 0, s,   \
                        b->inst_d, b->tile_prefix_d, b->group_first[gi], b->group_count[gi],     \
-                       b->group_tiles[gi], b->group_blocks[gi], b->order, (const double2 *)C_d, \
-                       (double2 *)HC_d)
+                       b->group_tiles[gi], b->group_blocks[gi], b->order, b->counters_d + gi,   \
+                       (const double2 *)b->coef_d, (const double2 *)C_d, (double2 *)HC_d)
         switch (b->group_kind[gi]) {
         case kPaperMap: MC_DISPATCH_M(M, if constexpr (MT > 0) MC_BATCH_LAUNCH(kPaperMap)); break;
         case kPaperChain: MC_DISPATCH_M(M, if constexpr (MT > 0) MC_BATCH_LAUNCH(kPaperChain)); break;

@@ -181,8 +181,12 @@ __device__ __forceinline__ int wave_in_block()
 // Maps a hardware block index to a logical one so that each of the 8 XCDs
 // (which receive blocks round-robin) works on a contiguous range of blocks;
 // neighbouring tiles then share the XCD's L2.
+#ifndef MC_XCD_REMAP
+#define MC_XCD_REMAP 1
+#endif
 __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb)
 {
+    if (!MC_XCD_REMAP) return b;
     const int64_t xcd = b & 7, local = b >> 3;
     const int64_t per = nb >> 3, rem = nb & 7;
     return xcd * per + (xcd < rem ? xcd : rem) + local;

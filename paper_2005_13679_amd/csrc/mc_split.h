@@ -605,7 +605,7 @@ __device__ __forceinline__ void apply_tile_split(int64_t tile, int64_t D, int64_
     }
 
     const __amdgpu_buffer_rsrc_t r1 = make_rsrc(t1 + tile * NS * kTile, (uint32_t)(NS * kTile * 4));
-    if constexpr (MAP && !kLdsRoots<MT> && FlatTile<MT>::NDBL > 0) {
+    if constexpr (MAP && MT <= 5 && FlatTile<MT>::NDBL > 0) {
         // every pair present and the block exactly the full size: one stream
         int64_t off0, off1;
         t2_block(t2_off, tile, cap, off0, off1);

@@ -60,7 +60,11 @@ def test_every_schedule_gives_identical_results(mc, small_batch):
     from paper_2005_13679_amd.batch import Batch
     insts, host = small_batch
     ref = None
-    for sched in CANDIDATES:
+    # plus thresholds that send every / some instances to launches of their own
+    extra = [{"blocks_per_cu": 2, "order": 3, "solo_tiles": 1},
+             {"blocks_per_cu": 1, "order": 0, "solo_tiles": 3},
+             {"blocks_per_cu": 2, "order": 1, "solo_tiles": 0}]
+    for sched in CANDIDATES + extra:
         b = Batch(insts, sched)
         C = batch_vector(b, [x[2] for x in host])
         out = b.apply_H(C, b.vector())
