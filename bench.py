@@ -169,6 +169,31 @@ def autograd_leg(dev) -> dict:
             "rho1_ms": rho1, "rho2_ms": rho2}
 
 
+def sil_leg(dev, N: int = 200, M: int = 5, dt: float = 1e-5, tol: float = 1e-10) -> dict:
+    """One Short Iterative Lanczos step exp(-i H dt) C on the throughput
+    workload (reduced tables), adaptive Krylov dimension up to 16."""
+    import torch
+    import paper_2005_13679_amd as mc
+    import workloads as W
+    C, h, g = W.random_instance(N, M, 2)
+    tab = mc.build_tables(N, M, dev, form="reduced")
+    hd, gd, Cd = (torch.from_numpy(x).to(dev) for x in (h, g, C))
+    st = mc.SILStepper(tab, hd, gd, kmax=16)
+    out = torch.empty_like(Cd)
+    st.step(Cd, dt, tol=tol, out=out)       # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out, m, err = st.step(Cd, dt, tol=tol, out=out)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    res = {"workload": f"N={N}, M={M}, dim {C.size}, reduced tables", "dt": dt, "tol": tol,
+           "krylov_dim": m, "error_estimate": err, "step_ms": sec * 1e3,
+           "ms_per_krylov_vector": sec * 1e3 / max(m, 1)}
+    del st, tab, out, Cd
+    torch.cuda.empty_cache()
+    return res
+
+
 def batched_leg(dev, steps: int = 50) -> dict:
     """64 seeded instances (N ~ U{8..40}, M ~ U{3..8}): 50 Lanczos steps for all
     of them in one captured graph (autotuned schedule) vs the same steps per
@@ -368,6 +393,8 @@ def main(argv=None):
         out["other_paths"] = others
         print("[bench] autograd leg (N=50, M=6)", file=sys.stderr, flush=True)
         out["autograd_vs_plain"] = autograd_leg(dev)
+        print("[bench] SIL propagation leg (N=200, M=5)", file=sys.stderr, flush=True)
+        out["sil_step"] = sil_leg(dev)
         print("[bench] batched leg (64 instances, 50 Lanczos steps)", file=sys.stderr, flush=True)
         out["batched_vs_plain"] = batched_leg(dev)
 

@@ -372,6 +372,20 @@ int mc_normalize(int64_t n, const double *w_d, double *out_d, double *beta_d, vo
 int mc_lanczos_orth(int64_t n, double *w_d, const double *v_d, const double *vprev_d,
                     const double *alpha_d, const double *beta_prev_d, mc_stream stream);
 
+/* out_d[i] = sum_{k<K} V_d[k*ldv + i] c_d[k] (complex128), k in order; the
+ * Krylov combination of a Short Iterative Lanczos step.  out_d must not
+ * overlap V_d (MC_EINVAL).  K >= 1. */
+int mc_zgemv_n(int32_t K, int64_t n, const double *V_d, int64_t ldv, const double *c_d,
+               double *out_d, mc_stream stream);
+
+/* y = exp(-i T dt) e_0 (y[2K], interleaved complex, host) for the real
+ * symmetric tridiagonal T with diagonal alpha[K] and off-diagonal beta[K-1]
+ * (host arrays), through the eigen-decomposition of T by cyclic Jacobi
+ * rotations: the small-matrix step of the Short Iterative Lanczos integrator
+ * that Sec. II names for time-dependent problems (C(t+dt) ~ |C| V_K y).
+ * 1 <= K <= 512, else MC_EINVAL.  Host only. */
+int mc_tridiag_expv(int32_t K, const double *alpha, const double *beta, double dt, double *y);
+
 /* Lowest eigenvalue of the real symmetric tridiagonal matrix with diagonal
  * alpha[K] and off-diagonal beta[K-1] (host arrays), by Sturm-sequence
  * bisection.  Host only. */

@@ -3,6 +3,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <vector>
+
 #include "mc_internal.h"
 
 namespace mc {
@@ -156,6 +158,68 @@ int mc_tables_size(int32_t N, int32_t M, mc_table_sizes *out)
     const int64_t pairs_total = N >= 2 ? dim_checked(N - 2, M) : 0;
     out->t2_compact_entries = (int64_t)M * M * npairs(M) * pairs_total;
     out->t2r_compact_entries = reduced_row_entries(M) * pairs_total;
+    return MC_OK;
+}
+
+// exp(-i T dt) e_0 for the real symmetric tridiagonal T (diagonal alpha[K],
+// off-diagonal beta[K-1]): eigen-decomposition T = Q diag(lambda) Q^T by
+// cyclic Jacobi rotations (each rotation zeroes one off-diagonal element of
+// the symmetric matrix; sweeps repeat until the off-diagonal mass is at
+// rounding level), then y = Q exp(-i lambda dt) Q^T e_0.
+int mc_tridiag_expv(int32_t K, const double *alpha, const double *beta, double dt, double *y)
+{
+    if (K < 1 || K > 512 || !alpha || !y || (K > 1 && !beta)) return MC_EINVAL;
+    std::vector<double> A((size_t)K * K, 0.0), Q((size_t)K * K, 0.0);
+    for (int i = 0; i < K; ++i) {
+        A[(size_t)i * K + i] = alpha[i];
+        Q[(size_t)i * K + i] = 1.0;
+        if (i + 1 < K) A[(size_t)i * K + i + 1] = A[(size_t)(i + 1) * K + i] = beta[i];
+    }
+    double scale = 0.0;
+    for (double v : A) scale += v * v;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0;
+        for (int p = 0; p < K; ++p)
+            for (int q = p + 1; q < K; ++q) off += A[(size_t)p * K + q] * A[(size_t)p * K + q];
+        if (off <= 1e-32 * scale) break;
+        for (int p = 0; p < K; ++p) {
+            for (int q = p + 1; q < K; ++q) {
+                const double apq = A[(size_t)p * K + q];
+                if (apq == 0.0) continue;
+                // rotation (c, s) with tan of the angle t the smaller root of
+                // t^2 + 2 theta t - 1 = 0, theta = (a_qq - a_pp) / (2 a_pq)
+                const double theta = (A[(size_t)q * K + q] - A[(size_t)p * K + p]) / (2.0 * apq);
+                const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+                for (int k = 0; k < K; ++k) {   // A <- A J (columns p, q)
+                    const double akp = A[(size_t)k * K + p], akq = A[(size_t)k * K + q];
+                    A[(size_t)k * K + p] = c * akp - sn * akq;
+                    A[(size_t)k * K + q] = sn * akp + c * akq;
+                }
+                for (int k = 0; k < K; ++k) {   // A <- J^T A (rows p, q)
+                    const double apk = A[(size_t)p * K + k], aqk = A[(size_t)q * K + k];
+                    A[(size_t)p * K + k] = c * apk - sn * aqk;
+                    A[(size_t)q * K + k] = sn * apk + c * aqk;
+                }
+                for (int k = 0; k < K; ++k) {   // Q <- Q J
+                    const double qkp = Q[(size_t)k * K + p], qkq = Q[(size_t)k * K + q];
+                    Q[(size_t)k * K + p] = c * qkp - sn * qkq;
+                    Q[(size_t)k * K + q] = sn * qkp + c * qkq;
+                }
+            }
+        }
+    }
+    for (int j = 0; j < K; ++j) {
+        double re = 0.0, im = 0.0;
+        for (int i = 0; i < K; ++i) {
+            const double lam = A[(size_t)i * K + i];
+            const double w = Q[(size_t)j * K + i] * Q[i];   // Q[0][i] = Q[i]
+            re += w * cos(lam * dt);
+            im -= w * sin(lam * dt);
+        }
+        y[2 * j] = re;
+        y[2 * j + 1] = im;
+    }
     return MC_OK;
 }
 

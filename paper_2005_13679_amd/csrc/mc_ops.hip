@@ -670,6 +670,23 @@ __global__ __launch_bounds__(256) void k_zgemv_sub(int K, int64_t n, const doubl
     }
 }
 
+// out[i] = sum_k V[k][i] c[k]  (the Krylov combination of a propagation step)
+__global__ __launch_bounds__(256) void k_zgemv_n(int K, int64_t n, const double2 *__restrict__ V,
+                                                  int64_t ldv, const double2 *__restrict__ c,
+                                                  double2 *__restrict__ out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double sr = 0.0, si = 0.0;
+        for (int k = 0; k < K; ++k) {
+            const double2 a = V[(int64_t)k * ldv + i], b = c[k];
+            sr += a.x * b.x - a.y * b.y;
+            si += a.x * b.y + a.y * b.x;
+        }
+        out[i] = make_double2(sr, si);
+    }
+}
+
 // beta = sqrt(Re <w|w>) from a finished zdotc result; out = w / beta
 __global__ __launch_bounds__(256) void k_normalize(int64_t n, const double2 *__restrict__ dot,
                                                    const double2 *__restrict__ w,
@@ -754,6 +771,20 @@ int mc_zgemv_sub(int32_t K, int64_t n, const double *V_d, int64_t ldv, const dou
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(k_zgemv_sub, dim3(blocks), dim3(256), 0, (hipStream_t)stream, K, n,
                        (const double2 *)V_d, ldv, (const double2 *)c_d, (double2 *)w_d);
+    return launch_status();
+}
+
+int mc_zgemv_n(int32_t K, int64_t n, const double *V_d, int64_t ldv, const double *c_d,
+               double *out_d, mc_stream stream)
+{
+    if (K < 1 || n < 0 || ldv < n) return MC_EINVAL;
+    if (n == 0) return MC_OK;
+    if (!V_d || !out_d || !c_d) return MC_EINVAL;
+    if (overlaps(V_d, (size_t)((K - 1) * ldv + n) * 16, out_d, (size_t)n * 16)) return MC_EINVAL;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_zgemv_n, dim3(blocks), dim3(256), 0, (hipStream_t)stream, K, n,
+                       (const double2 *)V_d, ldv, (const double2 *)c_d, (double2 *)out_d);
     return launch_status();
 }
 

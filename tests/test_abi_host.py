@@ -173,3 +173,24 @@ def test_device_entry_points_reject_bad_arguments_before_launch(lib):
     # wrong tile count
     t.tiles = 15
     assert lib.mc_build_jump_tables(10, 5, ctypes.byref(t), None) == -1
+
+
+@pytest.mark.parametrize("K", [1, 2, 3, 7, 20, 40])
+def test_tridiag_expv_matches_dense_expm(K):
+    """mc_tridiag_expv (host) = first column of exp(-i T dt), T symmetric tridiagonal."""
+    from scipy.linalg import expm
+    from paper_2005_13679_amd.propagate import tridiag_expv
+    rng = np.random.default_rng(K)
+    a = rng.standard_normal(K) * 5
+    b = np.abs(rng.standard_normal(max(0, K - 1)))
+    T = np.diag(a) + np.diag(b, 1) + np.diag(b, -1)
+    for dt in (0.0, 1e-3, 0.37, -1.5):
+        y = tridiag_expv(a, b, dt)
+        assert np.max(np.abs(y - expm(-1j * dt * T)[:, 0])) <= 1e-13
+
+
+def test_tridiag_expv_rejects_bad_sizes(lib):
+    y = np.zeros(2, dtype=np.float64)
+    a = np.zeros(1)
+    assert lib.mc_tridiag_expv(0, a.ctypes.data, None, 0.1, y.ctypes.data) == -1
+    assert lib.mc_tridiag_expv(513, a.ctypes.data, a.ctypes.data, 0.1, y.ctypes.data) == -1
