@@ -194,6 +194,47 @@ def sil_leg(dev, N: int = 200, M: int = 5, dt: float = 1e-5, tol: float = 1e-10)
     return res
 
 
+def lieb_liniger_leg(dev) -> dict:
+    """Plane-wave Lieb-Liniger ring (Sec. VI; momentum-conserving g): H.C at
+    N=40, M=7 (dim 9,366,819) through each path, and the Lanczos ground state
+    of N=20, M=7 (dim 230,230), gamma = 1, with the sparse apply."""
+    import torch
+    import paper_2005_13679_amd as mc
+    from paper_2005_13679_amd import lanczos
+    import workloads as W
+    res = {}
+    N, M = 40, 7
+    h = torch.from_numpy(W.lieb_liniger_h(M)).to(dev)
+    g = torch.from_numpy(W.lieb_liniger_g(M, 1.0 * N)).to(dev)
+    C = torch.from_numpy(W.random_coefficients(np.random.default_rng(1), W.fock_dim(N, M))).to(dev)
+    out = torch.empty_like(C)
+    stream = torch.cuda.current_stream(dev)
+    for name, form, maps, fn in (("paper_map", "paper", True, mc.apply_H),
+                                 ("reduced_map", "reduced", True, mc.apply_H),
+                                 ("sparse_reduced_map", "reduced", True, mc.apply_H_sparse),
+                                 ("sparse_chained", "reduced", False, mc.apply_H_sparse)):
+        tab = mc.build_tables(N, M, dev, double_jumps=maps, form=form)
+        fn(h, g, C, tab, out=out)
+        res[f"apply_ms_{name}"] = _median_ms(lambda: [fn(h, g, C, tab, out=out) for _ in range(10)],
+                                              3, stream) / 10
+        del tab
+        torch.cuda.empty_cache()
+    res["apply_workload"] = f"N={N}, M={M}, dim {C.numel()}, c = gamma N / L, gamma = 1"
+    N, M = 20, 7
+    h = torch.from_numpy(W.lieb_liniger_h(M)).to(dev)
+    g = torch.from_numpy(W.lieb_liniger_g(M, 1.0 * N)).to(dev)
+    tab = mc.build_tables(N, M, dev, form="reduced")
+    v0 = torch.from_numpy(W.random_coefficients(np.random.default_rng(2), tab.dim)).to(dev)
+    t0 = time.perf_counter()
+    e0, a, b, it = lanczos.ground_state(h, g, tab, v0, sparse=True)
+    torch.cuda.synchronize()
+    res["lanczos"] = {"workload": f"N={N}, M={M}, dim {tab.dim}, gamma = 1", "E0": e0,
+                      "iterations": int(it), "seconds": time.perf_counter() - t0}
+    del tab
+    torch.cuda.empty_cache()
+    return res
+
+
 def batched_leg(dev, steps: int = 50) -> dict:
     """64 seeded instances (N ~ U{8..40}, M ~ U{3..8}): 50 Lanczos steps for all
     of them in one captured graph (autotuned schedule) vs the same steps per
@@ -393,6 +434,8 @@ def main(argv=None):
         out["other_paths"] = others
         print("[bench] autograd leg (N=50, M=6)", file=sys.stderr, flush=True)
         out["autograd_vs_plain"] = autograd_leg(dev)
+        print("[bench] Lieb-Liniger leg (sparse apply, Lanczos)", file=sys.stderr, flush=True)
+        out["lieb_liniger"] = lieb_liniger_leg(dev)
         print("[bench] SIL propagation leg (N=200, M=5)", file=sys.stderr, flush=True)
         out["sil_step"] = sil_leg(dev)
         print("[bench] batched leg (64 instances, 50 Lanczos steps)", file=sys.stderr, flush=True)

@@ -239,6 +239,18 @@ int mc_apply_H_adjoint(int32_t N, int32_t M, const double *h_d, const double *g_
                        const mc_tables *t, const double *C_d, double *HC_d,
                        void *ws_d, size_t ws_bytes, mc_stream stream);
 
+/* HC_d = H . C_d in the case-split form of mc_apply_H, for interactions
+ * most of whose coefficients vanish (e.g. momentum conservation of the
+ * plane-wave g of the Lieb-Liniger model, Sec. VI: 44 of 462 true double
+ * jumps per row survive at M = 7, and no single-jump term).  After staging,
+ * one kernel lists the single jumps and reduced slots whose constants are not
+ * all zero; the apply gathers only those.  Needs reduced-form tables (with or
+ * without the map) and M <= 8, else MC_EINVAL; other arguments as mc_apply_H.
+ * Results equal mc_apply_H's up to rounding order for any g. */
+int mc_apply_H_sparse(int32_t N, int32_t M, const double *h_d, const double *g_d,
+                      const mc_tables *t, const double *C_d, double *HC_d,
+                      void *ws_d, size_t ws_bytes, mc_stream stream);
+
 /* rho1_d [M*M] = <a+_k a_l> (Eq. rho1) through the single-jump map.
  * Deterministic fixed-order reduction in ws_d (mc_workspace_size(RHO1)). */
 int mc_rho1(int32_t N, int32_t M, const mc_tables *t, const double *C_d,

@@ -215,6 +215,26 @@ def apply_H(h, g, C: torch.Tensor, tables: Tables, out: torch.Tensor | None = No
     return out
 
 
+def apply_H_sparse(h, g, C: torch.Tensor, tables: Tables,
+                   out: torch.Tensor | None = None) -> torch.Tensor:
+    """HC = H . C in the case-split form, gathering only the jumps whose
+    constants are nonzero (reduced-form tables; pays when most of g
+    vanishes, e.g. a momentum-conserving interaction)."""
+    N, M, dev = tables.N, tables.M, tables.device
+    h = _as_dev(h, dev, (M, M))
+    g = _as_dev(g, dev, (M, M, M, M))
+    _require(C, "C", torch.complex128, dev, numel=tables.dim)
+    if out is None:
+        out = torch.empty_like(C)
+    _require(out, "out", torch.complex128, dev, numel=tables.dim)
+    ws = tables.workspace(L.MC_OP_APPLY)
+    with torch.cuda.device(dev):
+        L.check(L.load().mc_apply_H_sparse(N, M, _ptr(h), _ptr(g), ctypes.byref(tables.c),
+                                           _ptr(C), _ptr(out), _ptr(ws), ws.numel(),
+                                           _stream(dev)), "mc_apply_H_sparse")
+    return out
+
+
 def apply_H_adjoint(h, g, C: torch.Tensor, tables: Tables,
                     out: torch.Tensor | None = None) -> torch.Tensor:
     """H^dagger . C (h -> h^dagger, g_ksql -> conj(g_lqsk))."""

@@ -13,6 +13,7 @@
 
 #include "mc_apply.h"
 #include "mc_split.h"
+#include "mc_sparse.h"
 #include "mc_internal.h"
 
 namespace mc {
@@ -68,6 +69,25 @@ __global__ void k_prep_split(int M, int adjoint, const double2 *__restrict__ g,
 {
     stage_split_constants(M, adjoint, g, h, cf, blockIdx.x * blockDim.x + threadIdx.x,
                           gridDim.x * blockDim.x);
+}
+
+// H.C in the case-split form walking only the nonzero constants (lists
+// built by k_sparse_lists); reduced tables, MAP as in k_apply_split.
+template <int MT, typename OccT, bool BIGC, bool MAP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MC_APPLY_WAVES)))
+void k_apply_sparse(int N, int64_t D, int64_t tiles, int64_t nblocks, int64_t cap,
+                    const OccT *__restrict__ occ, const int32_t *__restrict__ t1,
+                    const uint64_t *__restrict__ pmask, const int64_t *__restrict__ t2_off,
+                    const int32_t *__restrict__ t2r, const double2 *__restrict__ cf,
+                    const int32_t *__restrict__ sl, const double2 *__restrict__ C,
+                    double2 *__restrict__ HC)
+{
+    extern __shared__ double sq[];
+    fill_sqrt_table(sq, N + 3);
+    const int64_t tile = xcd_block(blockIdx.x, nblocks) * 4 + wave_in_block();
+    if (tile >= tiles) return;
+    apply_tile_sparse<MT, OccT, BIGC, MAP>(tile, D, cap, sq, occ, t1, pmask, t2_off, t2r, cf, sl,
+                                           C, HC);
 }
 
 // H.C in the case-split form (reduced tables); MAP: reduced double-jump map
@@ -831,10 +851,11 @@ int mc_workspace_size(int32_t N, int32_t M, int32_t op, size_t *bytes)
     const int64_t P = npairs(M);
     switch (op) {
     case MC_OP_APPLY: {
-        // staged constants of either form
-        const int64_t paper = P * M * M + M * M;
-        const int64_t split = M <= 8 ? split_total(M) : 0;
-        *bytes = (size_t)((paper > split ? paper : split) * 16);
+        // staged constants of either form (plus the sparse lists of the
+        // case-split form)
+        const int64_t paper = (P * M * M + M * M) * 16;
+        const int64_t split = M <= 8 ? split_total(M) * 16 + kSlInts * 4 : 0;
+        *bytes = (size_t)(paper > split ? paper : split);
         return MC_OK;
     }
     case MC_OP_RHO1: *bytes = (size_t)rho_waves(tiles) * M * M * 16; return MC_OK;
@@ -959,6 +980,56 @@ int mc_apply_H_adjoint(int32_t N, int32_t M, const double *h_d, const double *g_
                        size_t ws_bytes, mc_stream stream)
 {
     return apply_common(N, M, h_d, g_d, t, C_d, HC_d, ws_d, ws_bytes, 1, stream);
+}
+
+int mc_apply_H_sparse(int32_t N, int32_t M, const double *h_d, const double *g_d,
+                      const mc_tables *t, const double *C_d, double *HC_d, void *ws_d,
+                      size_t ws_bytes, mc_stream stream)
+{
+    int st = check_nm(N, M);
+    if (st) return st;
+    if (!t) return MC_EINVAL;
+    const bool chained = t->t2_d == nullptr;
+    st = check_tables(N, M, t, !chained);
+    if (st) return st;
+    if (t->form != MC_FORM_REDUCED || M > 8) return MC_EINVAL;
+    if (!h_d || !g_d || !C_d || !HC_d || !ws_d) return MC_EINVAL;
+    const int64_t D = t->dim;
+    if (overlaps(C_d, (size_t)D * 16, HC_d, (size_t)D * 16)) return MC_EINVAL;
+    size_t need = 0;
+    mc_workspace_size(N, M, MC_OP_APPLY, &need);
+    if (ws_bytes < need) return MC_ENOMEM;
+    const size_t sqb = (size_t)(N + 3) * 8;
+    if (sqb > 65536) return MC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    double2 *cf = (double2 *)ws_d;
+    int32_t *sl = (int32_t *)(cf + split_total(M));
+    hipLaunchKernelGGL(k_prep_split, dim3(4), dim3(256), 0, s, M, 0, (const double2 *)g_d,
+                       (const double2 *)h_d, cf);
+    hipLaunchKernelGGL(k_sparse_lists, dim3(1), dim3(64), 0, s, M, (const double2 *)cf, sl);
+    const int64_t nblocks = (t->tiles + 3) / 4;
+    const bool big = D * 16 > (int64_t)0xFFFFFFFFu;
+    bool launched = false;
+#define MC_SPARSE_LAUNCH(OT, BIG, MAP)                                                         \
+    MC_DISPATCH_M(M, if constexpr (MT > 0 && (MT <= 5 || sizeof(OT) == 1) && !(BIG && MAP)) {   \
+        hipLaunchKernelGGL((k_apply_sparse<MT, OT, BIG, MAP>), dim3(nblocks), dim3(256), sqb, s, \
+                           N, D, t->tiles, nblocks, t->t2_entries, (const OT *)t->occ_d,         \
+                           t->t1_d, t->pmask_d, t->t2_off_d, t->t2_d, (const double2 *)cf,       \
+                           (const int32_t *)sl, (const double2 *)C_d, (double2 *)HC_d);         \
+        launched = true;                                                                       \
+    })
+    if (chained) {
+        if (occ_width(N) == 1) {
+            if (big) { MC_SPARSE_LAUNCH(uint8_t, true, false); } else { MC_SPARSE_LAUNCH(uint8_t, false, false); }
+        } else {
+            if (big) { MC_SPARSE_LAUNCH(uint16_t, true, false); } else { MC_SPARSE_LAUNCH(uint16_t, false, false); }
+        }
+    } else if (!big) {
+        if (occ_width(N) == 1) { MC_SPARSE_LAUNCH(uint8_t, false, true); } else { MC_SPARSE_LAUNCH(uint16_t, false, true); }
+    }
+#undef MC_SPARSE_LAUNCH
+    if (!launched) return MC_EINVAL;
+    return launch_status();
 }
 
 int mc_rho1(int32_t N, int32_t M, const mc_tables *t, const double *C_d, double *rho1_d,

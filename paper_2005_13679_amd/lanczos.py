@@ -30,8 +30,10 @@ def tridiag_lowest(alphas, betas) -> float:
 
 
 def ground_state(h, g, tables, v0: torch.Tensor, max_iter: int = 300, tol: float = 1e-12,
-                 reorthogonalize: bool = True):
-    """Returns (E0, alphas, betas, iterations)."""
+                 reorthogonalize: bool = True, sparse: bool = False):
+    """Returns (E0, alphas, betas, iterations).  sparse=True applies H with
+    mc_apply_H_sparse (reduced-form tables; for interactions with many
+    vanishing coefficients such as the Lieb-Liniger g)."""
     dev, D = tables.device, tables.dim
     cap = int(min(max_iter, D))
     M = tables.M
@@ -59,7 +61,7 @@ def ground_state(h, g, tables, v0: torch.Tensor, max_iter: int = 300, tol: float
     prev, stable, e0 = None, 0, None
     for j in range(cap):
         cur = V[j] if reorthogonalize else V[j % 2]
-        api.apply_H(h, g, cur, tables, out=w)
+        (api.apply_H_sparse if sparse else api.apply_H)(h, g, cur, tables, out=w)
         api.zdotc(cur, w, out=alpha_d)
         if reorthogonalize:
             for _ in range(2):   # classical Gram-Schmidt, twice

@@ -152,7 +152,11 @@ def test_tables_size(lib):
 
 def test_workspace_size(lib):
     import paper_2005_13679_amd as mc
-    assert mc.workspace_size(10, 5, 1) == (15 * 25 + 25) * 16
+    # the larger of: paper-form constants (M^2 per pair + h), case-split
+    # constants (DL 5, GI 15, HS 25, GS 125, GD 110) plus the sparse lists
+    # (1 + 64 + 2*36 + 8*28 + 28*21 int32)
+    assert mc.workspace_size(10, 5, 1) == max((15 * 25 + 25) * 16,
+                                               (5 + 15 + 25 + 125 + 110) * 16 + (1 + 64 + 72 + 812) * 4)
     assert mc.workspace_size(10, 5, 2) > 0 and mc.workspace_size(10, 5, 3) > 0
     b = ctypes.c_size_t()
     assert lib.mc_workspace_size(10, 5, 99, ctypes.byref(b)) == -1

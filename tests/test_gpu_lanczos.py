@@ -45,9 +45,11 @@ def test_three_term_recurrence_matches_oracle(mc, oracle_native):
     assert np.allclose(b[: len(a) - 1], b2[: len(a) - 1], rtol=1e-10, atol=1e-10)
 
 
-def test_lieb_liniger_workload():
+@pytest.mark.parametrize("sparse", [False, True])
+def test_lieb_liniger_workload(sparse):
     """N = 20, plane waves up to M = 7 (dim 230,230): GPU Lanczos equals the
-    oracle's stored energies; variational and monotone in M."""
+    oracle's stored energies; variational and monotone in M.  sparse: the
+    apply walks only the momentum-conserving jumps (reduced tables)."""
     import paper_2005_13679_amd as mc
     from paper_2005_13679_amd import lanczos
     path = os.path.join(GOLDEN, "ll_energies.json")
@@ -57,9 +59,9 @@ def test_lieb_liniger_workload():
     for r in ref["runs"]:
         M = r["M"]
         h, g = W.lieb_liniger_h(M, L), W.lieb_liniger_g(M, r["c"], L)
-        tab = mc.build_tables(N, M)
+        tab = mc.build_tables(N, M, form="reduced" if sparse else "paper")
         v0 = W.random_coefficients(np.random.default_rng(1000 + M), tab.dim)
-        e, *_ = lanczos.ground_state(h, g, tab, dev(v0), max_iter=400, tol=1e-13)
+        e, *_ = lanczos.ground_state(h, g, tab, dev(v0), max_iter=400, tol=1e-13, sparse=sparse)
         assert abs(e - r["E0"]) <= 1e-9 * abs(r["E0"]), (r, e)
         assert e >= r["E_bethe"] - 1e-9
         by_gamma.setdefault(r["gamma"], []).append((M, e))
