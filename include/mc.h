@@ -258,7 +258,9 @@ int mc_rho1(int32_t N, int32_t M, const mc_tables *t, const double *C_d,
 
 /* rho2_d [M^4] = <a+_k a+_s a_q a_l> (Eq. rho2) through the double-jump map,
  * deterministic fixed-order reduction in ws_d (mc_workspace_size(RHO2)).
- * Needs a paper-form double-jump map (MC_EINVAL otherwise). */
+ * Needs a double-jump map (either form; in the reduced form the slots that
+ * share an orbital with the removal pair read the row itself or the
+ * single-jump map, App. B's coincident-index cases), M <= 8. */
 int mc_rho2(int32_t N, int32_t M, const mc_tables *t, const double *C_d,
             double *rho2_d, void *ws_d, size_t ws_bytes, mc_stream stream);
 

@@ -398,10 +398,14 @@ __global__ __launch_bounds__(256) void k_rho1(int N, int64_t D, int64_t tiles, i
 // rho2 for removal pair p = (k, s) (run-time), slots [J0, J0 + CH) of its
 // M*M creation pairs (compile-time).  The occupations of the lane's row are
 // also kept in LDS (occ_lds[m][lane]) so n_k, n_s need no register indexing.
-template <int MT, typename OccT, int J0>
+// RED: tables in the reduced form; a slot's configuration is then the row
+// itself ({q,l} = {k,s}), a single jump (one shared orbital: the unmatched
+// removal a and creation b give T1[a][b]) or a reduced-map entry.
+template <int MT, typename OccT, bool RED, int J0>
 __device__ __forceinline__ void rho2_chunk(int k, int s, int p, int64_t D, int64_t tiles,
                                            int nwaves, int wave, int64_t cap,
                                            const OccT *__restrict__ occ,
+                                           const int32_t *__restrict__ t1,
                                            const uint64_t *__restrict__ pmask,
                                            const int64_t *__restrict__ t2_off,
                                            const int32_t *__restrict__ t2,
@@ -419,18 +423,30 @@ __device__ __forceinline__ void rho2_chunk(int k, int s, int p, int64_t D, int64
     for (int64_t tile = wave; tile < tiles; tile += nwaves) {
         const uint64_t *pm = pmask + tile * W;
         if (!((pm[p >> 6] >> (p & 63)) & 1)) continue;   // no row of the tile can lose (k, s)
-        int64_t rank = 0;
+        // slots of the blocks before p's in this tile
+        int64_t before = 0;
+        if constexpr (RED) {
+            int pp = 0;
+            for (int a = 0; a < MT; ++a)
+                for (int b = a; b < MT; ++b, ++pp)
+                    if (pp < p && ((pm[pp >> 6] >> (pp & 63)) & 1)) before += reduced_slots(MT, a, b);
+        } else {
 #pragma unroll
-        for (int wd = 0; wd < W; ++wd) {
-            const uint64_t word = pm[wd];
-            if (wd < (p >> 6)) rank += __popcll(word);
-            else if (wd == (p >> 6)) rank += __popcll(word & (((uint64_t)1 << (p & 63)) - 1));
+            for (int wd = 0; wd < W; ++wd) {
+                const uint64_t word = pm[wd];
+                if (wd < (p >> 6)) before += __popcll(word);
+                else if (wd == (p >> 6)) before += __popcll(word & (((uint64_t)1 << (p & 63)) - 1));
+            }
+            before *= NS;
         }
+        const int BS = RED ? reduced_slots(MT, k, s) : NS;
         int64_t off0, off1;
         t2_block(t2_off, tile, cap, off0, off1);
-        const int64_t bs = off0 + rank * NS * kTile;
-        if (bs + NS * kTile > off1) continue;
-        const __amdgpu_buffer_rsrc_t r2 = make_rsrc(t2 + bs, (uint32_t)(NS * kTile * 4));
+        const int64_t bs = off0 + before * kTile;
+        if (bs + (int64_t)BS * kTile > off1) continue;
+        const __amdgpu_buffer_rsrc_t r2 = make_rsrc(t2 + bs, (uint32_t)(BS * kTile * 4));
+        const __amdgpu_buffer_rsrc_t r1 =
+            make_rsrc(t1 + tile * NS * kTile, (uint32_t)(NS * kTile * 4));
         const int64_t g = tile * kTile + lane;
         int n[MT];
 #pragma unroll
@@ -440,8 +456,30 @@ __device__ __forceinline__ void rho2_chunk(int k, int s, int p, int64_t D, int64
         }
         int32_t t[CH];
 #pragma unroll
-        for (int i = 0; i < CH; ++i)
-            t[i] = buf_ld_i32(r2, (uint32_t)(((J0 + i) * kTile + lane) * 4), 0);
+        for (int i = 0; i < CH; ++i) {
+            if constexpr (!RED) {
+                t[i] = buf_ld_i32(r2, (uint32_t)(((J0 + i) * kTile + lane) * 4), 0);
+            } else {
+                const int j = J0 + i, q = j / MT, l = j % MT;
+                // match {q, l} against the removal multiset {k, s}
+                bool mk = false, ms = false;
+                const bool qm = q == k || q == s;
+                if (q == k) mk = true; else if (q == s) ms = true;
+                bool lm = false;
+                if (l == k && !mk) { mk = true; lm = true; }
+                else if (l == s && !ms) { ms = true; lm = true; }
+                const int shared = (int)qm + (int)lm;
+                if (shared == 2) {
+                    t[i] = g < D ? (int32_t)g : -1;
+                } else if (shared == 1) {
+                    const int a = mk ? s : k, b = qm ? l : q;
+                    t[i] = buf_ld_i32(r1, (uint32_t)(((a * MT + b) * kTile + lane) * 4), 0);
+                } else {
+                    const int r = reduced_rank(MT, k, s, q < l ? q : l, q < l ? l : q);
+                    t[i] = buf_ld_i32(r2, (uint32_t)((r * kTile + lane) * 4), 0);
+                }
+            }
+        }
         const double2 cg = ldc(g < D ? (int32_t)g : -1);
         const int nk = occ_lds[k * kTile + lane], ns = occ_lds[s * kTile + lane];
         const bool valid = k == s ? nk >= 2 : (nk >= 1 && ns >= 1);
@@ -471,26 +509,28 @@ __device__ __forceinline__ void rho2_chunk(int k, int s, int p, int64_t D, int64
     }
 }
 
-template <int MT, typename OccT, int... Js>
+template <int MT, typename OccT, bool RED, int... Js>
 __device__ __forceinline__ void rho2_pair(std::integer_sequence<int, Js...>, int k, int s, int p,
                                           int64_t D, int64_t tiles, int nwaves, int wave,
                                           int64_t cap, const OccT *__restrict__ occ,
+                                          const int32_t *__restrict__ t1,
                                           const uint64_t *__restrict__ pmask,
                                           const int64_t *__restrict__ t2_off,
                                           const int32_t *__restrict__ t2, const Gather<false> &ldc,
                                           const double *sq, int *occ_lds,
                                           double2 *__restrict__ part)
 {
-    (rho2_chunk<MT, OccT, Js * kRhoChunk>(k, s, p, D, tiles, nwaves, wave, cap, occ, pmask, t2_off,
-                                          t2, ldc, sq, occ_lds, part),
+    (rho2_chunk<MT, OccT, RED, Js * kRhoChunk>(k, s, p, D, tiles, nwaves, wave, cap, occ, t1,
+                                               pmask, t2_off, t2, ldc, sq, occ_lds, part),
      ...);
 }
 
 // Dynamic LDS: sqrt table (N+3 doubles), then per wavefront an int
 // occupation row [M][64].
-template <int MT, typename OccT>
+template <int MT, typename OccT, bool RED>
 __global__ __launch_bounds__(256) void k_rho2(int N, int64_t D, int64_t tiles, int nwaves,
                                                int64_t cap, const OccT *__restrict__ occ,
+                                               const int32_t *__restrict__ t1,
                                                const uint64_t *__restrict__ pmask,
                                                const int64_t *__restrict__ t2_off,
                                                const int32_t *__restrict__ t2,
@@ -509,8 +549,9 @@ __global__ __launch_bounds__(256) void k_rho2(int N, int64_t D, int64_t tiles, i
     for (int k = 0; k < MT; ++k) {
 #pragma unroll 1
         for (int s = k; s < MT; ++s, ++p)
-            rho2_pair<MT, OccT>(std::make_integer_sequence<int, NCH>{}, k, s, p, D, tiles, nwaves,
-                                wave, cap, occ, pmask, t2_off, t2, ldc, sq, occ_lds, part);
+            rho2_pair<MT, OccT, RED>(std::make_integer_sequence<int, NCH>{}, k, s, p, D, tiles,
+                                     nwaves, wave, cap, occ, t1, pmask, t2_off, t2, ldc, sq,
+                                     occ_lds, part);
     }
 }
 
@@ -1083,7 +1124,8 @@ int mc_rho2(int32_t N, int32_t M, const mc_tables *t, const double *C_d, double 
     if (st) return st;
     st = check_tables(N, M, t, true);
     if (st) return st;
-    if (t->form != MC_FORM_PAPER || !C_d || !rho2_d || !ws_d) return MC_EINVAL;
+    if (!C_d || !rho2_d || !ws_d) return MC_EINVAL;
+    const bool red = t->form == MC_FORM_REDUCED;
     size_t need = 0;
     mc_workspace_size(N, M, MC_OP_RHO2, &need);
     if (ws_bytes < need) return MC_ENOMEM;
@@ -1093,20 +1135,20 @@ int mc_rho2(int32_t N, int32_t M, const mc_tables *t, const double *C_d, double 
     const bool big = D * 16 > (int64_t)0xFFFFFFFFu;
     double2 *part = (double2 *)ws_d;
     bool launched = false;
-#define MC_RHO2_LAUNCH(OT)                                                                      \
+#define MC_RHO2_LAUNCH(OT, RED)                                                                 \
     MC_DISPATCH_M(M, if constexpr (MT > 0 && (MT <= 5 || sizeof(OT) == 1)) {                      \
-        hipLaunchKernelGGL((k_rho2<MT, OT>), dim3((nw + 3) / 4), dim3(256), lds, s, N, D,          \
-                           t->tiles, nw, t->t2_entries, (const OT *)t->occ_d, t->pmask_d,         \
-                           t->t2_off_d, t->t2_d, (const double2 *)C_d, part);                    \
+        hipLaunchKernelGGL((k_rho2<MT, OT, RED>), dim3((nw + 3) / 4), dim3(256), lds, s, N, D,     \
+                           t->tiles, nw, t->t2_entries, (const OT *)t->occ_d, t->t1_d,            \
+                           t->pmask_d, t->t2_off_d, t->t2_d, (const double2 *)C_d, part);        \
         launched = true;                                                                         \
     })
     const size_t lds = (size_t)(N + 3) * 8 + (size_t)4 * M * kTile * 4;
     // the double-jump map cannot exist for D >= 2^28 (it would exceed HBM)
     if (M > 8 || lds > 65536 || big) return MC_EINVAL;
     if (occ_width(N) == 1) {
-        MC_RHO2_LAUNCH(uint8_t);
+        if (red) { MC_RHO2_LAUNCH(uint8_t, true); } else { MC_RHO2_LAUNCH(uint8_t, false); }
     } else {
-        MC_RHO2_LAUNCH(uint16_t);
+        if (red) { MC_RHO2_LAUNCH(uint16_t, true); } else { MC_RHO2_LAUNCH(uint16_t, false); }
     }
 #undef MC_RHO2_LAUNCH
     if (!launched) return MC_EINVAL;

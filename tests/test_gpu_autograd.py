@@ -43,10 +43,11 @@ def fd_check(mc, tab, C, h, g, hermitian, rng, ndir=4, eps=1e-6):
     return grads
 
 
-@pytest.mark.parametrize("N,M,seed", [(10, 5, 0), (6, 4, 1)])
-def test_gradients_fd_and_density_matrices(mc, oracle_native, N, M, seed):
+@pytest.mark.parametrize("N,M,seed,form", [(10, 5, 0, "paper"), (6, 4, 1, "paper"),
+                                           (10, 5, 0, "reduced"), (5, 6, 2, "reduced")])
+def test_gradients_fd_and_density_matrices(mc, oracle_native, N, M, seed, form):
     C, h, g = W.random_instance(N, M, seed)
-    tab = mc.build_tables(N, M)
+    tab = mc.build_tables(N, M, form=form)
     grads = fd_check(mc, tab, C, h, g, True, np.random.default_rng(seed))
     assert rel_inf(grads["h"], np.conj(oracle_native.rho1(N, M, C))) <= 1e-12
     assert rel_inf(grads["g"], 0.5 * np.conj(oracle_native.rho2(N, M, C))) <= 1e-12
@@ -54,12 +55,13 @@ def test_gradients_fd_and_density_matrices(mc, oracle_native, N, M, seed):
     assert rel_inf(grads["C"], 2 * HC) <= 1e-12
 
 
-def test_gradients_non_hermitian(mc):
+@pytest.mark.parametrize("form", ["paper", "reduced"])
+def test_gradients_non_hermitian(mc, form):
     N, M = 5, 3
     rng = np.random.default_rng(7)
     h = rng.standard_normal((M, M)) + 1j * rng.standard_normal((M, M))
     g = rng.standard_normal((M,) * 4) + 1j * rng.standard_normal((M,) * 4)
-    tab = mc.build_tables(N, M)
+    tab = mc.build_tables(N, M, form=form)
     C = W.random_coefficients(rng, tab.dim)
     fd_check(mc, tab, C, h, g, False, rng)
 

@@ -85,8 +85,28 @@ def test_split_large_space_sampled_rows(mc, oracle_native, double_jumps):
     torch.cuda.empty_cache()
 
 
-def test_rho2_needs_paper_map(mc):
-    tab = mc.build_tables(6, 4, form="reduced")
+@pytest.mark.parametrize("N,M,seed", [(1, 1, 0), (2, 2, 1), (4, 3, 2), (6, 4, 3), (10, 5, 4), (5, 6, 5),
+                                      (4, 7, 6), (3, 8, 7), (300, 2, 8), (40, 3, 9)])
+def test_rho_on_reduced_tables_matches_oracle(mc, oracle_native, N, M, seed):
+    C, _, _ = W.random_instance(N, M, seed)
+    tab = mc.build_tables(N, M, form="reduced")
+    Cd = dev(C)
+    r2 = mc.rho2(Cd, tab).cpu().numpy()
+    assert rel_inf(r2, oracle_native.rho2(N, M, C)) <= TOL
+    r1 = mc.rho1(Cd, tab).cpu().numpy()
+    assert rel_inf(r1, oracle_native.rho1(N, M, C)) <= TOL
+
+
+def test_rho2_agrees_across_forms(mc):
+    N, M = 30, 5
+    C, _, _ = W.random_instance(N, M, 10)
+    a = mc.rho2(dev(C), mc.build_tables(N, M)).cpu().numpy()
+    b = mc.rho2(dev(C), mc.build_tables(N, M, form="reduced")).cpu().numpy()
+    assert rel_inf(b, a) <= TOL
+
+
+def test_rho2_needs_a_map(mc):
+    tab = mc.build_tables(6, 4, form="reduced", double_jumps=False)
     C = torch.ones(tab.dim, dtype=torch.complex128, device="cuda")
     with pytest.raises(mc.MCError):
         mc.rho2(C, tab)
