@@ -205,8 +205,82 @@ __device__ __forceinline__ void split_pairs_map(std::integer_sequence<int, Ps...
         ...);
 }
 
+// Reduced slots of pair (K, S) among the ordered slots j = q*M + l in [J0, J1).
+__host__ __device__ constexpr int reduced_in_range(int M, int K, int S, int J0, int J1)
+{
+    int c = 0;
+    for (int j = J0; j < J1; ++j) {
+        const int q = j / M, l = j % M;
+        if (l >= q && reduced_slot(K, S, q, l)) ++c;
+    }
+    return c;
+}
+
+// Slots j in [J0, J1) of pair P through two chained single jumps, in a basic
+// block of its own (gathers of one part in flight at a time).
+template <int MT, bool BIGC, int P, int J0, int J1, bool OWN_BLOCK>
+__device__ __forceinline__ void split_chain_part(int64_t D, const int32_t *__restrict__ t1,
+                                                 int lane, const int32_t (&fh)[MT], bool valid,
+                                                 const RowSq<MT> &R,
+                                                 const double2 *__restrict__ gd,
+                                                 const Gather<BIGC> &ldc, double &br, double &bi)
+{
+    constexpr int K = pair_k(MT, P), S = pair_s(MT, P), NS = MT * MT;
+    constexpr int CO = reduced_pair_offset(MT, P);
+    constexpr int NA = reduced_in_range(MT, K, S, J0, J1);
+    constexpr int R0 = reduced_in_range(MT, K, S, 0, J0);
+    if constexpr (NA > 0) {
+        if constexpr (OWN_BLOCK)
+            if (!opaque_true()) return;
+        int32_t t[NA];
+        double2 c[NA];
+#pragma unroll
+        for (int j = J0; j < J1; ++j) {
+            const int q = j / MT, l = j % MT;
+            if (l < q || !reduced_slot(K, S, q, l)) continue;
+            const int r = reduced_rank(MT, K, S, q, l) - R0;
+            const int32_t b = fh[q];
+            const bool ok = valid && b >= 0 && b < D;
+            const int64_t bb = ok ? b : 0;
+            const int32_t v = t1[((bb >> 6) * NS + S * MT + l) * kTile + (bb & 63)];
+            t[r] = ok ? v : -1;
+        }
+#pragma unroll
+        for (int r = 0; r < NA; ++r) c[r] = ldc(t[r]);
+#pragma unroll
+        for (int j = J0; j < J1; ++j) {
+            const int q = j / MT, l = j % MT;
+            if (l < q || !reduced_slot(K, S, q, l)) continue;
+            const int r = reduced_rank(MT, K, S, q, l);
+            const double Bf = q == l ? R.template root<1>(q) * R.template root<2>(q)
+                                     : R.template root<1>(q) * R.template root<1>(l);
+            const double cr = c[r - R0].x * Bf, ci = c[r - R0].y * Bf;
+            const double2 Gv = gd[CO + r];
+            br = fma(Gv.x, cr, br);
+            br = fma(-Gv.y, ci, br);
+            bi = fma(Gv.x, ci, bi);
+            bi = fma(Gv.y, cr, bi);
+        }
+    }
+}
+
+template <int MT, bool BIGC, int P, int... Hs>
+__device__ __forceinline__ void split_chain_parts(std::integer_sequence<int, Hs...>, int64_t D,
+                                                  const int32_t *__restrict__ t1, int lane,
+                                                  const int32_t (&fh)[MT], bool valid,
+                                                  const RowSq<MT> &R,
+                                                  const double2 *__restrict__ gd,
+                                                  const Gather<BIGC> &ldc, double &br, double &bi)
+{
+    constexpr int NS = MT * MT, NH = sizeof...(Hs);
+    (split_chain_part<MT, BIGC, P, Hs * NS / NH, (Hs + 1) * NS / NH, (NH > 1)>(
+         D, t1, lane, fh, valid, R, gd, ldc, br, bi),
+     ...);
+}
+
 // The same pair through two chained single jumps: first K -> q from the
-// tile's own single-jump block, then S -> l from the intermediate row.
+// tile's own single-jump block, then S -> l from the intermediate row; the
+// slots in parts of at most 14 gathers.
 template <int MT, bool BIGC, int P>
 __device__ __forceinline__ void split_pair_chain(int64_t D, const int32_t *__restrict__ t1,
                                                  __amdgpu_buffer_rsrc_t r1, int lane,
@@ -215,8 +289,7 @@ __device__ __forceinline__ void split_pair_chain(int64_t D, const int32_t *__res
                                                  const Gather<BIGC> &ldc, double &ar, double &ai)
 {
     constexpr int K = pair_k(MT, P), S = pair_s(MT, P);
-    constexpr int ND = reduced_slots(MT, K, S), NS = MT * MT;
-    constexpr int CO = reduced_pair_offset(MT, P);
+    constexpr int ND = reduced_slots(MT, K, S);
     if constexpr (ND > 0) {
         const bool valid = K == S ? n[K] >= 2 : (n[K] >= 1 && n[S] >= 1);
         if (!__ballot(valid)) return;   // no row of the tile can lose (K, S)
@@ -226,38 +299,12 @@ __device__ __forceinline__ void split_pair_chain(int64_t D, const int32_t *__res
         int32_t fh[MT];
 #pragma unroll
         for (int q = 0; q < MT; ++q)
-            if (q != K && q != S)
-                fh[q] = buf_ld_i32(r1, (uint32_t)(((K * MT + q) * kTile + lane) * 4), 0);
-        int32_t t[ND];
-        double2 c[ND];
-#pragma unroll
-        for (int j = 0; j < NS; ++j) {
-            const int q = j / MT, l = j % MT;
-            if (l < q || !reduced_slot(K, S, q, l)) continue;
-            const int r = reduced_rank(MT, K, S, q, l);
-            const int32_t b = fh[q];
-            const bool ok = valid && b >= 0 && b < D;
-            const int64_t bb = ok ? b : 0;
-            const int32_t v = t1[((bb >> 6) * NS + S * MT + l) * kTile + (bb & 63)];
-            t[r] = ok ? v : -1;
-        }
-#pragma unroll
-        for (int r = 0; r < ND; ++r) c[r] = ldc(t[r]);
+            fh[q] = (q != K && q != S)
+                        ? buf_ld_i32(r1, (uint32_t)(((K * MT + q) * kTile + lane) * 4), 0)
+                        : -1;
         double br = 0.0, bi = 0.0;
-#pragma unroll
-        for (int j = 0; j < NS; ++j) {
-            const int q = j / MT, l = j % MT;
-            if (l < q || !reduced_slot(K, S, q, l)) continue;
-            const int r = reduced_rank(MT, K, S, q, l);
-            const double Bf = q == l ? R.template root<1>(q) * R.template root<2>(q)
-                                     : R.template root<1>(q) * R.template root<1>(l);
-            const double cr = c[r].x * Bf, ci = c[r].y * Bf;
-            const double2 Gv = gd[CO + r];
-            br = fma(Gv.x, cr, br);
-            br = fma(-Gv.y, ci, br);
-            bi = fma(Gv.x, ci, bi);
-            bi = fma(Gv.y, cr, bi);
-        }
+        split_chain_parts<MT, BIGC, P>(std::make_integer_sequence<int, (ND + 13) / 14>{}, D, t1,
+                                       lane, fh, valid, R, gd, ldc, br, bi);
         ar = fma(A, br, ar);
         ai = fma(A, bi, ai);
     }
@@ -385,6 +432,13 @@ __device__ __forceinline__ void split_pairs_loop(int64_t D, const int32_t *__res
 // while the current batch's gathers are in flight.  Same arithmetic, in the
 // same order, as the per-pair path.
 // ---------------------------------------------------------------------------
+// Largest M whose removal pairs are a compile-time fold (one basic block per
+// pair; chained pairs of more than 14 slots in parts of their own); above it
+// the pairs run as a loop (1.8x slower at M = 8).
+#ifndef MC_SPLIT_FOLD_MAX
+#define MC_SPLIT_FOLD_MAX 8
+#endif
+
 #ifndef MC_FLAT_BATCH
 #define MC_FLAT_BATCH 16
 #endif
@@ -669,14 +723,14 @@ __device__ __forceinline__ void apply_tile_split(int64_t tile, int64_t D, int64_
     if constexpr (MAP) {
         int64_t off0, off1;
         t2_block(t2_off, tile, cap, off0, off1);
-        if constexpr (kLdsRoots<MT>)
+        if constexpr (MT > MC_SPLIT_FOLD_MAX)
             split_pairs_loop<MT, BIGC, true>(D, t1, r1, pmask + tile * W, t2r, off0, off1, lane, n,
                                              sq, GD, ldc, ar, ai);
         else
             split_pairs_map<MT, BIGC>(std::make_integer_sequence<int, P>{}, pmask + tile * W, t2r,
                                       off0, off1, lane, n, R, GD, ldc, ar, ai);
     } else {
-        if constexpr (kLdsRoots<MT>)
+        if constexpr (MT > MC_SPLIT_FOLD_MAX)
             split_pairs_loop<MT, BIGC, false>(D, t1, r1, nullptr, nullptr, 0, 0, lane, n, sq, GD,
                                               ldc, ar, ai);
         else

@@ -122,3 +122,21 @@ def test_split_rejects_more_than_eight_orbitals(mc):
     g = torch.zeros((M,) * 4, dtype=torch.complex128, device="cuda")
     with pytest.raises(mc.MCError):
         mc.apply_H(h, g, C, tab)
+
+
+@pytest.mark.parametrize("form", ["reduced", "paper"])
+def test_chained_64bit_gathers_sampled_rows(mc, oracle_native, form):
+    """N = 300, M = 5: dim 348,881,876 > 2^28, so the coefficient gathers use
+    64-bit addresses (chained, no double-jump map; 16-bit occupations)."""
+    N, M = 300, 5
+    rng = np.random.default_rng(31)
+    D = oracle_native.dim(N, M)
+    C = W.random_coefficients(rng, D)
+    _, h, g = W.random_instance(1, M, 32)
+    tab = mc.build_tables(N, M, form=form, double_jumps=False)
+    hc = mc.apply_H(dev(h), dev(g), dev(C), tab)
+    rows = np.unique(np.concatenate([rng.integers(0, D, 1500), np.arange(64), D - 1 - np.arange(64)]))
+    got = hc[torch.from_numpy(rows).cuda()].cpu().numpy()
+    assert rel_inf(got, oracle_native.apply_h(N, M, h, g, C, rows)) <= TOL
+    del tab, hc
+    torch.cuda.empty_cache()
