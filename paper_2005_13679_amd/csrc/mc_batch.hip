@@ -63,12 +63,17 @@ constexpr int64_t kChunk = 1 << 16;
 constexpr int kMaxGroups = 32;   // 8 orbital counts x 4 kinds
 constexpr int kGrab = 8;         // tiles a wavefront takes per counter increment (order 3)
 
-// An instance launched on a grid of its own.
+// An instance launched on a grid of its own; its tables are passed to the
+// kernel as arguments (global, non-aliasing: the same loads as mc_apply_H).
 struct SoloLaunch {
     int32_t j;      // sorted position (index into the plan's descriptors)
-    int32_t M, kind;
-    int32_t pad;
-    int64_t tiles;
+    int32_t M, kind, N;
+    int64_t tiles, dim, cap, vec_off, gp_off, hp_off;
+    const uint8_t *occ;
+    const int32_t *t1;
+    const uint64_t *pmask;
+    const int64_t *t2_off;
+    const int32_t *t2;
 };
 
 }  // namespace mc
@@ -226,19 +231,29 @@ void k_batch_apply(const BatchInst *__restrict__ inst, const int64_t *__restrict
 }
 
 // One large instance on a grid of its own: one wavefront per tile, blocks
-// remapped per XCD as in the plain apply.
+// remapped per XCD as in the plain apply; tables, staged constants and the
+// instance's vector segments arrive as kernel arguments.
 template <int MT, int KIND>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MC_APPLY_WAVES)))
-void k_batch_solo(const BatchInst *__restrict__ ip, int64_t nblocks,
-                  const double2 *__restrict__ coef, const double2 *__restrict__ Cb,
-                  double2 *__restrict__ HCb)
+void k_batch_solo(int64_t D, int64_t tiles, int64_t nblocks, int64_t cap,
+                  const uint8_t *__restrict__ occ, const int32_t *__restrict__ t1,
+                  const uint64_t *__restrict__ pmask, const int64_t *__restrict__ t2_off,
+                  const int32_t *__restrict__ t2, const double2 *__restrict__ gp,
+                  const double2 *__restrict__ hp, const double2 *__restrict__ C,
+                  double2 *__restrict__ HC)
 {
     __shared__ double sq[kLdsRoots<MT> ? kBatchMaxN + 3 : 1];
     if constexpr (kLdsRoots<MT>) fill_sqrt_table(sq, kBatchMaxN + 3);
-    const BatchInst I = *ip;
     const int64_t tile = xcd_block(blockIdx.x, nblocks) * 4 + wave_in_block();
-    if (tile >= I.tiles) return;
-    batch_tile<MT, KIND>(I, tile, sq, coef, Cb, HCb);
+    if (tile >= tiles) return;
+    if constexpr (KIND == kPaperMap)
+        apply_tile_t2<MT, uint8_t, false>(tile, D, cap, sq, occ, t1, pmask, t2_off, t2, hp, gp, C,
+                                          HC);
+    else if constexpr (KIND == kPaperChain)
+        apply_tile_chained<MT, uint8_t, false>(tile, D, sq, occ, t1, hp, gp, C, HC);
+    else
+        apply_tile_split<MT, uint8_t, false, KIND == kSplitMap>(tile, D, cap, sq, occ, t1, pmask,
+                                                                t2_off, t2, gp, C, HC);
 }
 
 // Segmented conj(x).y: chunk partials, then per-instance sums in chunk order.
@@ -478,8 +493,17 @@ int mc_batch_create(int32_t count, const mc_batch_item *items, const mc_batch_sc
             L1.j = j;
             L1.M = t->M;
             L1.kind = I.kind;
-            L1.pad = 0;
+            L1.N = t->N;
             L1.tiles = t->tiles;
+            L1.dim = t->dim;
+            L1.cap = I.cap;
+            L1.gp_off = I.gp_off;
+            L1.hp_off = I.hp_off;
+            L1.occ = I.occ;
+            L1.t1 = I.t1;
+            L1.pmask = I.pmask;
+            L1.t2_off = I.t2_off;
+            L1.t2 = I.t2;
             prefix[j] = 0;
             continue;
         }
@@ -507,6 +531,7 @@ int mc_batch_create(int32_t count, const mc_batch_item *items, const mc_batch_sc
             voff += items[i].tables->dim;
         }
         for (int j = 0; j < count; ++j) inst[j].vec_off = off[sorted[j]];
+        for (int k = 0; k < b->nsolo; ++k) b->solo[k].vec_off = inst[b->solo[k].j].vec_off;
         for (int j = 0; j < count; ++j) {
             const int64_t D = inst[j].dim;
             for (int64_t s = 0; s < D; s += kChunk) {
@@ -580,14 +605,16 @@ int mc_batch_apply_H(const mc_batch *b, const double *C_d, double *HC_d, mc_stre
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(k_batch_prep, dim3(4, b->count), dim3(256), 0, s, b->inst_d, b->counters_d);
     for (int k = 0; k < b->nsolo; ++k) {
-        const int j = b->solo[k].j;
-        const int M = b->solo[k].M;
-        const int64_t nblocks = (b->solo[k].tiles + 3) / 4;
+        const SoloLaunch &L1 = b->solo[k];
+        const int M = L1.M;
+        const int64_t nblocks = (L1.tiles + 3) / 4;
 #define MC_SOLO_LAUNCH(KIND)                                                                    \
-    hipLaunchKernelGGL((k_batch_solo<MT, KIND>), dim3(nblocks), dim3(256), 0, s, b->inst_d + j,  \
-                       nblocks, (const double2 *)b->coef_d, (const double2 *)C_d,                 \
-                       (double2 *)HC_d)
-        switch (b->solo[k].kind) {
+    hipLaunchKernelGGL((k_batch_solo<MT, KIND>), dim3(nblocks), dim3(256), 0, s, L1.dim,         \
+                       L1.tiles, nblocks, L1.cap, L1.occ, L1.t1, L1.pmask, L1.t2_off, L1.t2,     \
+                       (const double2 *)b->coef_d + L1.gp_off,                                   \
+                       (const double2 *)b->coef_d + L1.hp_off,                                   \
+                       (const double2 *)C_d + L1.vec_off, (double2 *)HC_d + L1.vec_off)
+        switch (L1.kind) {
         case kPaperMap: MC_DISPATCH_M(M, if constexpr (MT > 0) MC_SOLO_LAUNCH(kPaperMap)); break;
         case kPaperChain: MC_DISPATCH_M(M, if constexpr (MT > 0) MC_SOLO_LAUNCH(kPaperChain)); break;
         case kSplitMap: MC_DISPATCH_M(M, if constexpr (MT > 0) MC_SOLO_LAUNCH(kSplitMap)); break;
