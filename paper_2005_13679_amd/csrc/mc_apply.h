@@ -20,7 +20,7 @@
 // are in flight (within a pair); 2 = also the first batch of the next block
 // (across pairs, and the first block during the one-body part).
 #ifndef MC_T2_PIPELINE
-#define MC_T2_PIPELINE 2
+#define MC_T2_PIPELINE 0
 #endif
 
 namespace mc {
@@ -140,6 +140,10 @@ __host__ __device__ constexpr int pair_s(int M, int p)
 // loads, then all its gathers, then the arithmetic.
 template <int MT>
 constexpr int kSlotBatch = MT * MT < MC_SLOT_BATCH ? MT * MT : MC_SLOT_BATCH;
+// Double-jump blocks of the paper form: a whole M*M block per batch up to
+// M = 5 (fastest measured at M = 5; larger M would spill).
+template <int MT>
+constexpr int kT2Batch = MT * MT <= 25 ? MT * MT : kSlotBatch<MT>;
 
 // Indices of slots [J0, J0 + SB) of a double-jump block (one per lane).
 template <int MT, int SB, int J0>
@@ -174,13 +178,13 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t t2_block_rsrc(const int32_t *t
 template <int MT, bool BIGC, int B, int NB>
 __device__ __forceinline__ void pair_batches(const int32_t *t2, int64_t pos, int64_t off1, int lane,
                                              __amdgpu_buffer_rsrc_t r2,
-                                             int32_t (&tf)[kSlotBatch<MT>],
-                                             int32_t (&tn)[kSlotBatch<MT>], const double (&rq)[MT],
+                                             int32_t (&tf)[kT2Batch<MT>],
+                                             int32_t (&tn)[kT2Batch<MT>], const double (&rq)[MT],
                                              const double (&dq)[MT], const double2 *__restrict__ G,
                                              const Gather<BIGC> &ldc, double &br, double &bi)
 {
     if constexpr (B < NB) {
-        constexpr int NS = MT * MT, SB = kSlotBatch<MT>, J0 = B * SB;
+        constexpr int NS = MT * MT, SB = kT2Batch<MT>, J0 = B * SB;
         double2 c[SB];
         if constexpr (MC_T2_PIPELINE == 0) {
             // indices of this batch, then its gathers
@@ -221,10 +225,10 @@ template <int MT, bool BIGC, int P>
 __device__ __forceinline__ void pair_term(const int32_t *t2, int64_t pos, int64_t off1, int lane,
                                           const int (&n)[MT], const RowSq<MT> &R,
                                           const double2 *__restrict__ gp, const Gather<BIGC> &ldc,
-                                          int32_t (&tf)[kSlotBatch<MT>], double &ar, double &ai)
+                                          int32_t (&tf)[kT2Batch<MT>], double &ar, double &ai)
 {
     constexpr int K = pair_k(MT, P), S = pair_s(MT, P);
-    constexpr int NS = MT * MT, SB = kSlotBatch<MT>;
+    constexpr int NS = MT * MT, SB = kT2Batch<MT>;
     constexpr int NB = (NS + SB - 1) / SB;
     const __amdgpu_buffer_rsrc_t r2 = make_rsrc(t2 + pos, (uint32_t)(NS * kTile * 4));
     const bool valid = K == S ? n[K] >= 2 : (n[K] >= 1 && n[S] >= 1);
@@ -255,7 +259,7 @@ __device__ __forceinline__ void all_pairs(std::integer_sequence<int, Ps...>,
                                           const uint64_t *pm, const int32_t *t2, int64_t off0,
                                           int64_t off1, int lane, const int (&n)[MT],
                                           const RowSq<MT> &R, const double2 *__restrict__ gp,
-                                          const Gather<BIGC> &ldc, int32_t (&tf)[kSlotBatch<MT>],
+                                          const Gather<BIGC> &ldc, int32_t (&tf)[kT2Batch<MT>],
                                           double &ar, double &ai)
 {
     int64_t pos = off0;
@@ -296,9 +300,9 @@ __device__ __forceinline__ void apply_tile_t2(int64_t tile, int64_t D, int64_t c
     // during the one-body part
     int64_t off0, off1;
     t2_block(t2_off, tile, cap, off0, off1);
-    int32_t tf[kSlotBatch<MT>];
+    int32_t tf[kT2Batch<MT>];
     if constexpr (MC_T2_PIPELINE == 2)
-        load_t2_batch<MT, kSlotBatch<MT>, 0>(tf, t2_block_rsrc(t2, off0, off1, M * M), lane);
+        load_t2_batch<MT, kT2Batch<MT>, 0>(tf, t2_block_rsrc(t2, off0, off1, M * M), lane);
 
     int n[M];
     RowSq<M> R;

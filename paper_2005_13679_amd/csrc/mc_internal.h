@@ -178,11 +178,14 @@ __device__ __forceinline__ int wave_in_block()
     return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 }
 
-// Maps a hardware block index to a logical one so that each of the 8 XCDs
-// (which receive blocks round-robin) works on a contiguous range of blocks;
-// neighbouring tiles then share the XCD's L2.
+// Maps a hardware block index to a logical one.  With MC_XCD_REMAP = 1 each
+// of the 8 XCDs (which receive blocks round-robin) works on a contiguous
+// range of blocks, so neighbouring tiles share the XCD's L2.  For the H.C
+// gathers the identity is faster (measured 2-8 %): an XCD's L2 cannot hold
+// the coefficient windows of its range anyway, and interleaved blocks let the
+// 8 XCDs share one working set in the memory-side cache.
 #ifndef MC_XCD_REMAP
-#define MC_XCD_REMAP 1
+#define MC_XCD_REMAP 0
 #endif
 __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb)
 {
