@@ -194,6 +194,26 @@ def sil_leg(dev, N: int = 200, M: int = 5, dt: float = 1e-5, tol: float = 1e-10)
     return res
 
 
+def hbm_reference(dev, gib: float = 8.0) -> dict:
+    """Achievable streaming rates on this GPU, for reading the roofline
+    fractions: a device-to-device copy and a read-only reduction of `gib` GiB
+    (torch's own kernels; context, not part of the path)."""
+    import torch
+    n = int(gib * (1 << 30)) // 8
+    src = torch.ones(n, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream(dev)
+    dst.copy_(src)
+    copy_ms = _median_ms(lambda: dst.copy_(src), 5, stream)
+    src.sum()
+    read_ms = _median_ms(lambda: src.sum(), 5, stream)
+    del src, dst
+    torch.cuda.empty_cache()
+    nbytes = n * 8
+    return {"copy_GB_per_s": 2 * nbytes / (copy_ms * 1e-3) / 1e9,
+            "read_GB_per_s": nbytes / (read_ms * 1e-3) / 1e9, "size_GiB": gib}
+
+
 def lieb_liniger_leg(dev) -> dict:
     """Plane-wave Lieb-Liniger ring (Sec. VI; momentum-conserving g): H.C at
     N=40, M=7 (dim 9,366,819) through each path, and the Lanczos ground state
@@ -432,6 +452,8 @@ def main(argv=None):
             del t2
             torch.cuda.empty_cache()
         out["other_paths"] = others
+        print("[bench] HBM streaming reference", file=sys.stderr, flush=True)
+        out["hbm_reference"] = hbm_reference(dev)
         print("[bench] autograd leg (N=50, M=6)", file=sys.stderr, flush=True)
         out["autograd_vs_plain"] = autograd_leg(dev)
         print("[bench] Lieb-Liniger leg (sparse apply, Lanczos)", file=sys.stderr, flush=True)

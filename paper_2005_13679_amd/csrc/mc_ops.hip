@@ -313,6 +313,17 @@ __global__ __launch_bounds__(256) void k_rho1_generic(int Mrt, int64_t D, int64_
 // ---------------------------------------------------------------------------
 constexpr int kRhoChunk = 32;   // slots accumulated per pass
 
+// Bit p set for the removal pairs p = (k, k) (lexicographic pair order).
+__host__ __device__ constexpr uint64_t diag_pair_mask(int M)
+{
+    uint64_t m = 0;
+    int p = 0;
+    for (int k = 0; k < M; ++k)
+        for (int s = k; s < M; ++s, ++p)
+            if (k == s) m |= (uint64_t)1 << p;
+    return m;
+}
+
 
 // rho1: elements e = k*M + l, chunk [J0, J0 + CH) of them per pass
 template <int MT, typename OccT, bool BIGC, int J0>
@@ -426,10 +437,13 @@ __device__ __forceinline__ void rho2_chunk(int k, int s, int p, int64_t D, int64
         // slots of the blocks before p's in this tile
         int64_t before = 0;
         if constexpr (RED) {
-            int pp = 0;
-            for (int a = 0; a < MT; ++a)
-                for (int b = a; b < MT; ++b, ++pp)
-                    if (pp < p && ((pm[pp >> 6] >> (pp & 63)) & 1)) before += reduced_slots(MT, a, b);
+            // block sizes depend only on k == s: count the present pairs
+            // before p of each kind (pair bits of k == s in kDiag)
+            static_assert(NP <= 64, "one mask word");
+            constexpr uint64_t kDiag = diag_pair_mask(MT);
+            const uint64_t below = pm[0] & (((uint64_t)1 << p) - 1);
+            before = (int64_t)__popcll(below & kDiag) * reduced_slots(MT, 0, 0) +
+                     (int64_t)__popcll(below & ~kDiag) * (MT >= 2 ? reduced_slots(MT, 0, 1) : 0);
         } else {
 #pragma unroll
             for (int wd = 0; wd < W; ++wd) {

@@ -1,0 +1,32 @@
+"""bench.py's host-side contract (CPU only): one GPU, byte models."""
+
+import math
+import os
+import subprocess
+import sys
+
+from tests.conftest import ROOT
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_byte_models():
+    sys.path.insert(0, ROOT)
+    import bench
+    N, M = 200, 5
+    D = math.comb(N + M - 1, N)
+    nc2 = math.comb(N - 2 + M - 1, N - 2)
+    paper = bench.algorithmic_bytes(N, M, "paper_map")
+    assert paper["t2"] == 4 * 25 * 15 * nc2            # M^2 slots per removal pair
+    assert abs(paper["total"] - 111.156e9) < 1e6
+    red = bench.algorithmic_bytes(N, M, "reduced_map")
+    assert red["t2"] == 4 * 110 * nc2                  # true double jumps of a full row
+    chained = bench.algorithmic_bytes(N, M, "reduced_chained")
+    assert chained["t2"] == 0 and chained["offsets"] == 0
+    assert chained["total"] == 4 * 25 * D + 5 * D + 32 * D
