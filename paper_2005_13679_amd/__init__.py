@@ -28,10 +28,11 @@ from .api import (
     zdotc,
 )
 from .autograd import Energy, energy
+from .batch import Batch, BatchedLanczos, batched_lanczos
 from .propagate import SILStepper, sil_step
 
 __all__ = [
-    "MCError", "LIB_PATH", "SILStepper", "sil_step", "Energy", "Tables", "apply_H", "apply_H_adjoint", "apply_H_sparse", "energy", "build_tables", "dim", "hash_batch",
+    "MCError", "LIB_PATH", "SILStepper", "sil_step", "Batch", "BatchedLanczos", "batched_lanczos", "Energy", "Tables", "apply_H", "apply_H_adjoint", "apply_H_sparse", "energy", "build_tables", "dim", "hash_batch",
     "hash_occ", "rho1", "rho2", "t2_lookup", "tables_size", "unhash", "unhash_batch",
     "workspace_size", "zaxpby", "zdotc",
 ]

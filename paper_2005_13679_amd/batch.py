@@ -216,3 +216,19 @@ def plain_lanczos(tables, h, g, v0: torch.Tensor, steps: int = 50):
                                         P(betas[j - 1]) if j > 0 else None, st), "orth")
             L.check(lib.mc_normalize(D, P(w), P(nxt), P(betas[j]), P(ws), ws.numel(), st), "norm")
     return alphas, betas[:steps]
+
+
+def batched_lanczos(instances, steps: int = 50, v0: torch.Tensor | None = None,
+                    schedule: dict | None = None, graph: bool = True, seed: int = 0):
+    """``steps`` three-term Lanczos steps for every instance [(tables, h, g),
+    ...] at once (one captured graph by default).  v0 is a batch vector (a
+    seeded complex-normal start per instance if None).  Returns
+    (alphas [steps, count], betas [steps, count]) as host arrays."""
+    b = Batch(instances, schedule)
+    if v0 is None:
+        rng = np.random.default_rng(seed)
+        v0 = b.vector()
+        for i, (t, _, _) in enumerate(instances):
+            x = rng.standard_normal(t.dim) + 1j * rng.standard_normal(t.dim)
+            b.segment(v0, i).copy_(torch.from_numpy(x))
+    return BatchedLanczos(b, steps, graph=graph).run(v0)

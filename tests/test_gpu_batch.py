@@ -144,3 +144,10 @@ def test_batch_rejects_unsupported(mc):
     tab = mc.build_tables(300, 2)   # N > 255: 16-bit occupations
     with pytest.raises(mc.MCError):
         Batch([(tab, np.eye(2), np.zeros((2, 2, 2, 2)))])
+
+
+def test_batched_lanczos_convenience(mc, small_batch):
+    insts, _ = small_batch
+    a1, b1 = mc.batched_lanczos(insts, steps=6, seed=3)
+    a2, b2 = mc.batched_lanczos(insts, steps=6, seed=3, graph=False)
+    assert a1.shape == (6, len(insts)) and np.array_equal(a1, a2) and np.array_equal(b1, b2)
