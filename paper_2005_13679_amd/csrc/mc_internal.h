@@ -187,9 +187,21 @@ __device__ __forceinline__ int wave_in_block()
 #ifndef MC_XCD_REMAP
 #define MC_XCD_REMAP 0
 #endif
+// MC_XCD_CHUNK = K > 1 (with the remap off): each XCD takes contiguous chunks
+// of K blocks, chunks interleaved over the XCDs (blocks past the last whole
+// group of 8K map to themselves).
+#ifndef MC_XCD_CHUNK
+#define MC_XCD_CHUNK 1
+#endif
 __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb)
 {
-    if (!MC_XCD_REMAP) return b;
+    if (!MC_XCD_REMAP) {
+        if (MC_XCD_CHUNK <= 1) return b;
+        const int64_t full = nb / (8 * MC_XCD_CHUNK) * (8 * MC_XCD_CHUNK);
+        if (b >= full) return b;
+        const int64_t x = b & 7, i = b >> 3;
+        return ((i / MC_XCD_CHUNK) * 8 + x) * MC_XCD_CHUNK + i % MC_XCD_CHUNK;
+    }
     const int64_t xcd = b & 7, local = b >> 3;
     const int64_t per = nb >> 3, rem = nb & 7;
     return xcd * per + (xcd < rem ? xcd : rem) + local;

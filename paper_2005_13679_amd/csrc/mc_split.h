@@ -321,109 +321,6 @@ __device__ __forceinline__ void split_pairs_chain(std::integer_sequence<int, Ps.
     (split_pair_chain<MT, BIGC, Ps>(D, t1, r1, lane, n, R, gd, ldc, ar, ai), ...);
 }
 
-// M >= 6: the removal pairs as a loop (K, S wave-uniform), creation pairs
-// q <= l compile-time with the excluded ones (sharing an orbital with
-// {K, S}) masked to index -1.  Roots from the block's sqrt table.  MAP
-// selects the reduced map (block at `pos` per present pair) or chaining.
-template <int MT, bool BIGC, bool MAP>
-__device__ __forceinline__ void split_pairs_loop(int64_t D, const int32_t *__restrict__ t1,
-                                                 __amdgpu_buffer_rsrc_t r1, const uint64_t *pm,
-                                                 const int32_t *t2r, int64_t off0, int64_t off1,
-                                                 int lane, const int (&n)[MT], const double *sq,
-                                                 const double2 *__restrict__ gd,
-                                                 const Gather<BIGC> &ldc, double &ar, double &ai)
-{
-    constexpr int NQ = MT * (MT + 1) / 2, NS = MT * MT;
-    constexpr int SB = NQ < MC_SLOT_BATCH ? NQ : MC_SLOT_BATCH;
-    double rq[MT], dq[MT];
-#pragma unroll
-    for (int q = 0; q < MT; ++q) {
-        rq[q] = sq[n[q] + 1];
-        dq[q] = sq[n[q] + 2];
-    }
-    int64_t pos = off0;
-    int P = 0, co = 0;
-#pragma unroll 1
-    for (int K = 0; K < MT; ++K) {
-#pragma unroll 1
-        for (int S = K; S < MT; ++S, ++P) {
-            const int ND = reduced_slots(MT, K, S);
-            const int cbase = co;
-            co += ND;
-            bool present;
-            __amdgpu_buffer_rsrc_t r2;
-            if constexpr (MAP) {
-                present = ((pm[P >> 6] >> (P & 63)) & 1) && ND > 0 &&
-                          pos + (int64_t)ND * kTile <= off1;
-                if (!present) continue;
-                r2 = make_rsrc(t2r + pos, (uint32_t)(ND * kTile * 4));
-                pos += (int64_t)ND * kTile;
-            }
-            int nK = 0, nS = 0;
-#pragma unroll
-            for (int m = 0; m < MT; ++m) {
-                nK = m == K ? n[m] : nK;
-                nS = m == S ? n[m] : nS;
-            }
-            const bool valid = K == S ? nK >= 2 : (nK >= 1 && nS >= 1);
-            if (ND == 0 || !__ballot(valid)) continue;
-            const double A = valid ? sq[nK] * (K == S ? sq[nK > 0 ? nK - 1 : 0] : sq[nS]) : 0.0;
-            int32_t fh[MT];
-            if constexpr (!MAP) {
-#pragma unroll
-                for (int q = 0; q < MT; ++q)
-                    fh[q] = buf_ld_i32(r1, (uint32_t)(((K * MT + q) * kTile + lane) * 4), 0);
-            }
-            double br = 0.0, bi = 0.0;
-#pragma unroll
-            for (int u0 = 0; u0 < NQ; u0 += SB) {
-                if (!opaque_true()) continue;   // one basic block per batch
-                int32_t t[SB];
-                double2 c[SB];
-#pragma unroll
-                for (int i = 0; i < SB; ++i) {
-                    // u -> (q, l), q <= l, lexicographic
-                    const int u = u0 + i;
-                    if (u >= NQ) break;
-                    const int q = pair_k(MT, u), l = pair_s(MT, u);
-                    const bool use = reduced_slot(K, S, q, l);
-                    if constexpr (MAP) {
-                        const int r = use ? reduced_rank(MT, K, S, q, l) : 0;
-                        const int32_t v = buf_ld_i32(r2, (uint32_t)((r * kTile + lane) * 4), 0);
-                        t[i] = use ? v : -1;
-                    } else {
-                        const int32_t b = fh[q];
-                        const bool ok = use && valid && b >= 0 && b < D;
-                        const int64_t bb = ok ? b : 0;
-                        const int32_t v = t1[((bb >> 6) * NS + S * MT + l) * kTile + (bb & 63)];
-                        t[i] = ok ? v : -1;
-                    }
-                }
-#pragma unroll
-                for (int i = 0; i < SB; ++i)
-                    if (u0 + i < NQ) c[i] = ldc(t[i]);
-#pragma unroll
-                for (int i = 0; i < SB; ++i) {
-                    const int u = u0 + i;
-                    if (u >= NQ) break;
-                    const int q = pair_k(MT, u), l = pair_s(MT, u);
-                    const bool use = reduced_slot(K, S, q, l);
-                    const int r = use ? reduced_rank(MT, K, S, q, l) : 0;
-                    const double Bf = q == l ? rq[q] * dq[q] : rq[q] * rq[l];
-                    const double2 Gv = use ? gd[cbase + r] : make_double2(0.0, 0.0);
-                    const double cr = c[i].x * Bf, ci = c[i].y * Bf;
-                    br = fma(Gv.x, cr, br);
-                    br = fma(-Gv.y, ci, br);
-                    bi = fma(Gv.x, ci, bi);
-                    bi = fma(Gv.y, cr, bi);
-                }
-            }
-            ar = fma(A, br, ar);
-            ai = fma(A, bi, ai);
-        }
-    }
-}
-
 // ---------------------------------------------------------------------------
 // Tiles whose pair mask has every pair (nearly all tiles of large spaces):
 // the tile's single jumps and reduced-map blocks form one stream of
@@ -432,13 +329,6 @@ __device__ __forceinline__ void split_pairs_loop(int64_t D, const int32_t *__res
 // while the current batch's gathers are in flight.  Same arithmetic, in the
 // same order, as the per-pair path.
 // ---------------------------------------------------------------------------
-// Largest M whose removal pairs are a compile-time fold (one basic block per
-// pair; chained pairs of more than 14 slots in parts of their own); above it
-// the pairs run as a loop (1.8x slower at M = 8).
-#ifndef MC_SPLIT_FOLD_MAX
-#define MC_SPLIT_FOLD_MAX 8
-#endif
-
 #ifndef MC_FLAT_BATCH
 #define MC_FLAT_BATCH 16
 #endif
@@ -719,23 +609,18 @@ __device__ __forceinline__ void apply_tile_split(int64_t tile, int64_t D, int64_
         }
     }
 
-    // true double jumps
+    // true double jumps: a compile-time fold over the removal pairs, one
+    // basic block per pair (chained pairs of more than 14 slots in parts of
+    // their own), so every orbital index is a constant and nothing spills up
+    // to M = 8
     if constexpr (MAP) {
         int64_t off0, off1;
         t2_block(t2_off, tile, cap, off0, off1);
-        if constexpr (MT > MC_SPLIT_FOLD_MAX)
-            split_pairs_loop<MT, BIGC, true>(D, t1, r1, pmask + tile * W, t2r, off0, off1, lane, n,
-                                             sq, GD, ldc, ar, ai);
-        else
-            split_pairs_map<MT, BIGC>(std::make_integer_sequence<int, P>{}, pmask + tile * W, t2r,
-                                      off0, off1, lane, n, R, GD, ldc, ar, ai);
+        split_pairs_map<MT, BIGC>(std::make_integer_sequence<int, P>{}, pmask + tile * W, t2r, off0,
+                                  off1, lane, n, R, GD, ldc, ar, ai);
     } else {
-        if constexpr (MT > MC_SPLIT_FOLD_MAX)
-            split_pairs_loop<MT, BIGC, false>(D, t1, r1, nullptr, nullptr, 0, 0, lane, n, sq, GD,
-                                              ldc, ar, ai);
-        else
-            split_pairs_chain<MT, BIGC>(std::make_integer_sequence<int, P>{}, D, t1, r1, lane, n, R,
-                                        GD, ldc, ar, ai);
+        split_pairs_chain<MT, BIGC>(std::make_integer_sequence<int, P>{}, D, t1, r1, lane, n, R, GD,
+                                    ldc, ar, ai);
     }
     if (live) HC[g] = make_double2(ar, ai);
 }
