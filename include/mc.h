@@ -251,6 +251,24 @@ int mc_apply_H_sparse(int32_t N, int32_t M, const double *h_d, const double *g_d
                       const mc_tables *t, const double *C_d, double *HC_d,
                       void *ws_d, size_t ws_bytes, mc_stream stream);
 
+/* HC_d = H . C_d with no table: the case-split sum of mc_apply_H, with each
+ * row's occupations and each jump target computed from the row's index in
+ * closed form instead of read from the hashing table and the jump maps.
+ * Summing Eq. TotalCost over the particles of each orbital gives
+ *   g = D - 1 - sum_{m=0}^{M-2} C(S_m + m, m + 1),  S_m = n_0 + ... + n_m,
+ * so the occupations follow from g greedily and a jump, which shifts a few
+ * S_m by at most 2, changes g by a sum of at most M-1 precomputed per-row
+ * differences (the O(M) index delta; Sec. III, IV).  Needs no mc_tables:
+ * device memory is C_d, HC_d and the workspace only, which lifts the table
+ * memory limit on N.  1 <= M <= 8 and D < 2^31 (else MC_EINVAL / MC_ERANGE),
+ * (N+3)*8 <= 65536; ws_d: mc_workspace_size(APPLY) bytes (staged constants,
+ * so concurrent calls need separate ws); HC_d must not overlap C_d.  The
+ * terms and their order are those of mc_apply_H on reduced-form tables, so
+ * the results agree with it up to the sign of zero. */
+int mc_apply_H_direct(int32_t N, int32_t M, const double *h_d, const double *g_d,
+                      const double *C_d, double *HC_d, void *ws_d, size_t ws_bytes,
+                      mc_stream stream);
+
 /* rho1_d [M*M] = <a+_k a_l> (Eq. rho1) through the single-jump map.
  * Deterministic fixed-order reduction in ws_d (mc_workspace_size(RHO1)). */
 int mc_rho1(int32_t N, int32_t M, const mc_tables *t, const double *C_d,

@@ -235,6 +235,34 @@ def apply_H_sparse(h, g, C: torch.Tensor, tables: Tables,
     return out
 
 
+_direct_ws: dict = {}
+
+
+def apply_H_direct(h, g, C: torch.Tensor, N: int, M: int,
+                   out: torch.Tensor | None = None) -> torch.Tensor:
+    """HC = H . C with no table: occupations and jump targets of every row
+    from its index in closed form (M <= 8, dim < 2^31).  Device memory is C,
+    out and a small workspace only."""
+    dev = C.device if isinstance(C, torch.Tensor) else torch.device("cuda")
+    D = dim(N, M)
+    h = _as_dev(h, dev, (M, M))
+    g = _as_dev(g, dev, (M, M, M, M))
+    _require(C, "C", torch.complex128, dev, numel=D)
+    if out is None:
+        out = torch.empty_like(C)
+    _require(out, "out", torch.complex128, dev, numel=D)
+    key = (dev, N, M)
+    ws = _direct_ws.get(key)
+    if ws is None:
+        ws = torch.empty(max(16, workspace_size(N, M, L.MC_OP_APPLY)), dtype=torch.uint8,
+                         device=dev)
+        _direct_ws[key] = ws
+    with torch.cuda.device(dev):
+        L.check(L.load().mc_apply_H_direct(N, M, _ptr(h), _ptr(g), _ptr(C), _ptr(out), _ptr(ws),
+                                           ws.numel(), _stream(dev)), "mc_apply_H_direct")
+    return out
+
+
 def apply_H_adjoint(h, g, C: torch.Tensor, tables: Tables,
                     out: torch.Tensor | None = None) -> torch.Tensor:
     """H^dagger . C (h -> h^dagger, g_ksql -> conj(g_lqsk))."""

@@ -14,6 +14,7 @@
 #include "mc_apply.h"
 #include "mc_split.h"
 #include "mc_sparse.h"
+#include "mc_direct.h"
 #include "mc_internal.h"
 
 namespace mc {
@@ -105,6 +106,20 @@ void k_apply_split(int N, int64_t D, int64_t tiles, int64_t nblocks, int64_t cap
     const int64_t tile = xcd_block(blockIdx.x, nblocks) * 4 + wave_in_block();
     if (tile >= tiles) return;
     apply_tile_split<MT, OccT, BIGC, MAP>(tile, D, cap, sq, occ, t1, pmask, t2_off, t2r, cf, C, HC);
+}
+
+// H.C with no table (occupations and targets in closed form, mc_direct.h).
+template <int MT, bool BIGC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MC_APPLY_WAVES)))
+void k_apply_direct(int N, int nbits, int64_t D, int64_t tiles, int64_t nblocks,
+                    const double2 *__restrict__ cf, const double2 *__restrict__ C,
+                    double2 *__restrict__ HC)
+{
+    extern __shared__ double sq[];
+    if constexpr (kLdsRoots<MT>) fill_sqrt_table(sq, N + 3);
+    const int64_t tile = xcd_block(blockIdx.x, nblocks) * 4 + wave_in_block();
+    if (tile >= tiles) return;
+    apply_tile_direct<MT, BIGC>(tile, N, nbits, D, sq, cf, C, HC);
 }
 
 template <int MT, typename OccT, bool BIGC>
@@ -1084,6 +1099,44 @@ int mc_apply_H_sparse(int32_t N, int32_t M, const double *h_d, const double *g_d
     }
 #undef MC_SPARSE_LAUNCH
     if (!launched) return MC_EINVAL;
+    return launch_status();
+}
+
+int mc_apply_H_direct(int32_t N, int32_t M, const double *h_d, const double *g_d,
+                      const double *C_d, double *HC_d, void *ws_d, size_t ws_bytes,
+                      mc_stream stream)
+{
+    int st = check_nm(N, M);
+    if (st) return st;
+    if (M > 8) return MC_EINVAL;
+    const int64_t D = dim_checked(N, M);
+    if (D < 0 || D >= ((int64_t)1 << 31)) return MC_ERANGE;
+    if (!h_d || !g_d || !C_d || !HC_d || !ws_d) return MC_EINVAL;
+    if (overlaps(C_d, (size_t)D * 16, HC_d, (size_t)D * 16)) return MC_EINVAL;
+    size_t need = 0;
+    mc_workspace_size(N, M, MC_OP_APPLY, &need);
+    if (ws_bytes < need) return MC_ENOMEM;
+    const size_t sqb = (size_t)(N + 3) * 8;
+    if (sqb > 65536) return MC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    double2 *cf = (double2 *)ws_d;
+    hipLaunchKernelGGL(k_prep_split, dim3(4), dim3(256), 0, s, M, 0, (const double2 *)g_d,
+                       (const double2 *)h_d, cf);
+    const int64_t tiles = (D + kTile - 1) / kTile;
+    const int64_t nblocks = (tiles + 3) / 4;
+    int nbits = 0;
+    while ((1 << nbits) <= N) ++nbits;   // bit width of N
+    const bool big = D * 16 > (int64_t)0xFFFFFFFFu;
+    MC_DISPATCH_M(M, if constexpr (MT > 0 && MT <= 8) {
+        if (big)
+            hipLaunchKernelGGL((k_apply_direct<MT, true>), dim3(nblocks), dim3(256),
+                               kLdsRoots<MT> ? sqb : 0, s, N, nbits, D, tiles, nblocks,
+                               (const double2 *)cf, (const double2 *)C_d, (double2 *)HC_d);
+        else
+            hipLaunchKernelGGL((k_apply_direct<MT, false>), dim3(nblocks), dim3(256),
+                               kLdsRoots<MT> ? sqb : 0, s, N, nbits, D, tiles, nblocks,
+                               (const double2 *)cf, (const double2 *)C_d, (double2 *)HC_d);
+    });
     return launch_status();
 }
 

@@ -177,6 +177,10 @@ def test_device_entry_points_reject_bad_arguments_before_launch(lib):
     # wrong tile count
     t.tiles = 15
     assert lib.mc_build_jump_tables(10, 5, ctypes.byref(t), None) == -1
+    # the table-free apply: M > 8, D >= 2^31 (N = 600, M = 5: D = 5.4e9), null buffers
+    assert lib.mc_apply_H_direct(10, 9, None, None, None, None, None, 0, None) == -1
+    assert lib.mc_apply_H_direct(600, 5, None, None, None, None, None, 0, None) == -2
+    assert lib.mc_apply_H_direct(10, 5, None, None, None, None, None, 0, None) == -1
 
 
 @pytest.mark.parametrize("K", [1, 2, 3, 7, 20, 40])

@@ -1,0 +1,102 @@
+"""GPU H.C with no table (mc_apply_H_direct: occupations and jump targets of
+each row from its index in closed form) vs the oracle, relative
+infinity-norm error <= 1e-12, and against the case-split apply on reduced
+tables, which sums the same terms in the same order."""
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from tests.gpu_helpers import rel_inf
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+# M = 1..8, single-tile spaces, ragged last tiles, N > 255, N = 1
+CASES = [(1, 1, 0), (3, 1, 1), (1, 4, 2), (2, 2, 3), (3, 5, 4), (10, 5, 0), (7, 4, 5), (5, 7, 6),
+         (6, 8, 7), (12, 6, 8), (20, 3, 9), (300, 2, 12), (256, 3, 13), (40, 4, 14), (14, 8, 10),
+         (20, 7, 11), (2, 3, 15), (1, 8, 16), (63, 2, 17), (64, 2, 18)]
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+@pytest.mark.parametrize("N,M,seed", CASES)
+def test_direct_matches_oracle_and_split(mc, oracle_native, N, M, seed):
+    C, h, g = W.random_instance(N, M, seed)
+    got = mc.apply_H_direct(dev(h), dev(g), dev(C), N, M)
+    assert rel_inf(got.cpu().numpy(), oracle_native.apply_h(N, M, h, g, C)) <= TOL
+    split = mc.apply_H(dev(h), dev(g), dev(C), mc.build_tables(N, M, form="reduced",
+                                                               double_jumps=False))
+    assert torch.equal(got, split)
+
+
+@pytest.mark.parametrize("N,M", [(4, 3), (10, 5), (6, 6), (5, 8), (3, 2), (9, 7)])
+def test_direct_general_complex_inputs(mc, oracle_native, N, M):
+    """No symmetry of h or g, C not normalised."""
+    rng = np.random.default_rng(N * 10 + M)
+    h = rng.standard_normal((M, M)) + 1j * rng.standard_normal((M, M))
+    g = rng.standard_normal((M,) * 4) + 1j * rng.standard_normal((M,) * 4)
+    D = oracle_native.dim(N, M)
+    C = rng.standard_normal(D) + 1j * rng.standard_normal(D)
+    got = mc.apply_H_direct(dev(h), dev(g), dev(C), N, M).cpu().numpy()
+    assert rel_inf(got, oracle_native.apply_h(N, M, h, g, C)) <= TOL
+
+
+def test_direct_lieb_liniger_workload(mc, oracle_native):
+    """N = 20, M = 7 (dim 230,230), the plane-wave Lieb-Liniger Hamiltonian."""
+    N, M = 20, 7
+    h = W.lieb_liniger_h(M)
+    g = W.lieb_liniger_g(M, c=20.0)
+    C = W.random_coefficients(np.random.default_rng(3), oracle_native.dim(N, M))
+    got = mc.apply_H_direct(dev(h), dev(g), dev(C), N, M)
+    rows = np.unique(np.concatenate([np.random.default_rng(4).integers(0, C.size, 3000),
+                                     np.arange(64), C.size - 1 - np.arange(64)]))
+    ref = oracle_native.apply_h(N, M, h, g, C, rows)
+    assert rel_inf(got[torch.from_numpy(rows).cuda()].cpu().numpy(), ref) <= TOL
+
+
+def test_direct_large_space_sampled_rows(mc, oracle_native):
+    """N = 200, M = 5 (dim 70,058,751), the throughput workload, in the launch
+    configuration the benchmark times; equal to the reduced-map apply."""
+    N, M = 200, 5
+    C, h, g = W.random_instance(N, M, 2)
+    Cd = dev(C)
+    hc = mc.apply_H_direct(dev(h), dev(g), Cd, N, M)
+    rng = np.random.default_rng(3)
+    D = C.size
+    rows = np.unique(np.concatenate([rng.integers(0, D, 2000), np.arange(128), D - 1 - np.arange(128)]))
+    got = hc[torch.from_numpy(rows).cuda()].cpu().numpy()
+    assert rel_inf(got, oracle_native.apply_h(N, M, h, g, C, rows)) <= TOL
+    tab = mc.build_tables(N, M, form="reduced")
+    ref = mc.apply_H(dev(h), dev(g), Cd, tab)
+    assert torch.equal(hc, ref)
+    del tab, ref, hc, Cd
+    torch.cuda.empty_cache()
+
+
+def test_direct_64bit_gathers_sampled_rows(mc, oracle_native):
+    """N = 300, M = 5: dim 348,881,876 > 2^28, 64-bit coefficient gathers."""
+    N, M = 300, 5
+    rng = np.random.default_rng(31)
+    D = oracle_native.dim(N, M)
+    C = W.random_coefficients(rng, D)
+    _, h, g = W.random_instance(1, M, 32)
+    hc = mc.apply_H_direct(dev(h), dev(g), dev(C), N, M)
+    rows = np.unique(np.concatenate([rng.integers(0, D, 1500), np.arange(64), D - 1 - np.arange(64)]))
+    got = hc[torch.from_numpy(rows).cuda()].cpu().numpy()
+    assert rel_inf(got, oracle_native.apply_h(N, M, h, g, C, rows)) <= TOL
+    del hc
+    torch.cuda.empty_cache()
+
+
+def test_direct_rejects_bad_sizes(mc):
+    z = lambda *s: torch.zeros(s, dtype=torch.complex128, device="cuda")
+    with pytest.raises(mc.MCError):            # M > 8
+        mc.apply_H_direct(z(9, 9), z(9, 9, 9, 9), z(mc.dim(1, 9)), 1, 9)
+    C = z(mc.dim(4, 3))
+    with pytest.raises(mc.MCError):            # output aliases the input
+        mc.apply_H_direct(z(3, 3), z(3, 3, 3, 3), C, 4, 3, out=C)
