@@ -40,6 +40,7 @@ PATHS = {
     "reduced_chained": ("reduced", False),  # case-split sum, true double jumps chained
     "paper_map": ("paper", True),          # the paper's sum and double-jump map
     "paper_chained": ("paper", False),     # the paper's sum, every slot chained
+    "direct": (None, False),               # case-split sum, no table: targets in closed form
 }
 # dominant kernel of each path (the one the roofline and profiles refer to)
 KERNELS = {
@@ -47,6 +48,7 @@ KERNELS = {
     "reduced_chained": "k_apply_split<5, uint8, false, MAP=false>",
     "paper_map": "k_apply<5, uint8, false>",
     "paper_chained": "k_apply_chained<5, uint8, false>",
+    "direct": "k_apply_direct<5, false>",
 }
 
 
@@ -56,9 +58,14 @@ def algorithmic_bytes(N: int, M: int, path: str = "reduced_map") -> dict:
     per valid removal pair, M^2 * M(M+1)/2 * N_c(N-2, M) entries; reduced: the
     true double jumps, [M * M(M-1)/2 + M(M-1)/2 * (M-1)(M-2)/2] * N_c(N-2, M)
     entries; none when chained), per-row offsets (D+1 int64, with a map),
-    occupations (M D uint8), coefficients in and out (16 D each)."""
+    occupations (M D uint8), coefficients in and out (16 D each).  The
+    table-free path reads no table: coefficients in and out only."""
     form, has_map = PATHS[path]
     D = math.comb(N + M - 1, N)
+    if form is None:
+        parts = {"coefficients_in": 16 * D, "coefficients_out": 16 * D}
+        parts["total"] = sum(parts.values())
+        return parts
     nc2 = math.comb(N - 2 + M - 1, N - 2) if N >= 2 else 0
     if form == "paper":
         per_row = M * M * (M * (M + 1) // 2)
@@ -78,7 +85,7 @@ def algorithmic_bytes(N: int, M: int, path: str = "reduced_map") -> dict:
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("mc_ops.hip", "mc_internal.h", "mc_apply.h", "mc_split.h"):
+    for f in ("mc_ops.hip", "mc_internal.h", "mc_apply.h", "mc_split.h", "mc_direct.h"):
         with open(os.path.join(ROOT, "paper_2005_13679_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -122,6 +129,15 @@ def cpu_baseline(N, M, h, g, C, budget_s: float = 15.0) -> dict:
         "sample": f"{n} seeded random rows of the {D}-row apply in {dt:.1f} s "
                   f"({n / dt:.0f} rows/s), scaled by rows",
     }
+
+
+def make_apply(mc, name, N, M, dev, hd, gd, Cd, HC):
+    """(apply closure, tables or None) of one path."""
+    form, has_map = PATHS[name]
+    if form is None:
+        return (lambda: mc.apply_H_direct(hd, gd, Cd, N, M, out=HC)), None
+    tab = mc.build_tables(N, M, dev, double_jumps=has_map, form=form)
+    return (lambda: mc.apply_H(hd, gd, Cd, tab, out=HC)), tab
 
 
 def _median_ms(fn, reps, stream):
@@ -351,16 +367,17 @@ def main(argv=None):
     C, h, g = W.random_instance(N, M, seed)
     D = C.size
     form, has_map = PATHS[args.path]
-    t0 = time.perf_counter()
-    tab = mc.build_tables(N, M, dev, double_jumps=has_map, form=form)
-    torch.cuda.synchronize()
-    build_s = time.perf_counter() - t0
-    print(f"[bench] tables built in {build_s:.2f} s ({sum(tab.nbytes().values()) / 1e9:.2f} GB)",
-          file=sys.stderr, flush=True)
     Cd = torch.from_numpy(C).to(dev)
     hd = torch.from_numpy(h).to(dev)
     gd = torch.from_numpy(g).to(dev)
     HC = torch.empty_like(Cd)
+    t0 = time.perf_counter()
+    apply, tab = make_apply(mc, args.path, N, M, dev, hd, gd, Cd, HC)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    tab_bytes = tab.nbytes() if tab is not None else {}
+    print(f"[bench] tables built in {build_s:.2f} s ({sum(tab_bytes.values()) / 1e9:.2f} GB)",
+          file=sys.stderr, flush=True)
 
     if args.copy_calibration_gib > 0:
         n = int(args.copy_calibration_gib * (1 << 30)) // 8
@@ -372,13 +389,13 @@ def main(argv=None):
         del src, dst
 
     for _ in range(args.warmup):
-        mc.apply_H(hd, gd, Cd, tab, out=HC)
+        apply()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream(dev)
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     start.record(stream)
     for _ in range(args.steps):
-        mc.apply_H(hd, gd, Cd, tab, out=HC)
+        apply()
     end.record(stream)
     torch.cuda.synchronize()
     ms = start.elapsed_time(end) / args.steps
@@ -415,10 +432,10 @@ def main(argv=None):
         },
         "algorithmic_bytes_per_apply": B["total"],
         "table_build_s": build_s,
-        "table_bytes": tab.nbytes(),
+        "table_bytes": tab_bytes,
     }
 
-    if args.extras:
+    if args.extras and tab is not None:
         extras = {}
         for name, fn in (("rho1", lambda: mc.rho1(Cd, tab)), ("rho2", lambda: mc.rho2(Cd, tab))):
             fn()
@@ -432,24 +449,24 @@ def main(argv=None):
         out["extras"] = extras
 
     if not args.quick:
-        del tab
+        del apply, tab
         torch.cuda.empty_cache()
         others = {}
         for name, (f2, m2) in PATHS.items():
             if name == args.path:
                 continue
             print(f"[bench] path {name}", file=sys.stderr, flush=True)
-            t2 = mc.build_tables(N, M, dev, double_jumps=m2, form=f2)
+            ap2, t2 = make_apply(mc, name, N, M, dev, hd, gd, Cd, HC)
             for _ in range(2):
-                mc.apply_H(hd, gd, Cd, t2, out=HC)
-            ms2 = _median_ms(lambda: [mc.apply_H(hd, gd, Cd, t2, out=HC) for _ in range(5)], 3,
-                             stream) / 5
+                ap2()
+            ms2 = _median_ms(lambda: [ap2() for _ in range(5)], 3, stream) / 5
             B2 = algorithmic_bytes(N, M, name)["total"]
             others[name] = {"ms_per_apply": ms2, "applies_per_s": 1e3 / ms2,
                             "algorithmic_bytes": B2, "GB_per_s": B2 / (ms2 * 1e-3) / 1e9,
                             "frac_of_hbm_peak": B2 / (ms2 * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                            "table_bytes": sum(t2.nbytes().values()), "kernel": KERNELS[name]}
-            del t2
+                            "table_bytes": sum(t2.nbytes().values()) if t2 is not None else 0,
+                            "kernel": KERNELS[name]}
+            del ap2, t2
             torch.cuda.empty_cache()
         out["other_paths"] = others
         print("[bench] HBM streaming reference", file=sys.stderr, flush=True)

@@ -220,6 +220,37 @@ __device__ __forceinline__ void direct_batches(const DirectRow<MT> &row, const i
     }
 }
 
+// With MC_DIRECT_PIPE: batch B's block first issues batch B+1's gathers
+// into the other buffer, then does batch B's arithmetic.
+#ifndef MC_DIRECT_PIPE
+#define MC_DIRECT_PIPE 0
+#endif
+
+template <int MT, bool BIGC, int B>
+__device__ __forceinline__ void direct_batches_pipe(double2 (&cur)[DirectStream<MT>::SB],
+                                                    double2 (&nxt)[DirectStream<MT>::SB],
+                                                    const DirectRow<MT> &row, const int (&n)[MT],
+                                                    const RowSq<MT> &R, const double (&x)[MT],
+                                                    const double2 *__restrict__ HS,
+                                                    const double2 *__restrict__ GS,
+                                                    const double2 *__restrict__ GD,
+                                                    const Gather<BIGC> &ldc, double &br,
+                                                    double &bi, double &ar, double &ai)
+{
+    constexpr int SB = DirectStream<MT>::SB, NB = DirectStream<MT>::NB;
+    if constexpr (B < NB) {
+        if (opaque_true()) {
+            if constexpr (B + 1 < NB)
+                direct_gathers<MT, BIGC, (B + 1) * SB>(std::make_integer_sequence<int, SB>{}, nxt,
+                                                       row, n, ldc);
+            direct_fmas<MT, B * SB>(std::make_integer_sequence<int, SB>{}, cur, n, R, x, HS, GS,
+                                    GD, br, bi, ar, ai);
+        }
+        direct_batches_pipe<MT, BIGC, B + 1>(nxt, cur, row, n, R, x, HS, GS, GD, ldc, br, bi, ar,
+                                             ai);
+    }
+}
+
 // One 64-row tile of H.C with no table (M <= 8, D < 2^31); `cf` holds the
 // constants staged by k_prep_split.
 template <int MT, bool BIGC>
@@ -270,7 +301,14 @@ __device__ __forceinline__ void apply_tile_direct(int64_t tile, int N, int nbits
     }
     // single jumps, then the true double jumps pair by pair
     double br = 0.0, bi = 0.0;
-    direct_batches<MT, BIGC, 0>(row, n, R, x, HS, GS, GD, ldc, br, bi, ar, ai);
+    if constexpr (MC_DIRECT_PIPE && DirectStream<MT>::NB > 1) {
+        double2 ca[DirectStream<MT>::SB], cb[DirectStream<MT>::SB];
+        direct_gathers<MT, BIGC, 0>(std::make_integer_sequence<int, DirectStream<MT>::SB>{}, ca,
+                                    row, n, ldc);
+        direct_batches_pipe<MT, BIGC, 0>(ca, cb, row, n, R, x, HS, GS, GD, ldc, br, bi, ar, ai);
+    } else {
+        direct_batches<MT, BIGC, 0>(row, n, R, x, HS, GS, GD, ldc, br, bi, ar, ai);
+    }
     if (live) HC[g] = make_double2(ar, ai);
 }
 

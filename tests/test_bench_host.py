@@ -30,3 +30,6 @@ def test_byte_models():
     chained = bench.algorithmic_bytes(N, M, "reduced_chained")
     assert chained["t2"] == 0 and chained["offsets"] == 0
     assert chained["total"] == 4 * 25 * D + 5 * D + 32 * D
+    direct = bench.algorithmic_bytes(N, M, "direct")
+    assert direct["total"] == 32 * D                   # no table: C in, HC out
+    assert set(bench.PATHS) == set(bench.KERNELS)
