@@ -271,21 +271,27 @@ def lieb_liniger_leg(dev) -> dict:
     return res
 
 
-def batched_leg(dev, steps: int = 50) -> dict:
+def batched_leg(dev, steps: int = 50, table_free: bool = False) -> dict:
     """64 seeded instances (N ~ U{8..40}, M ~ U{3..8}): 50 Lanczos steps for all
     of them in one captured graph (autotuned schedule) vs the same steps per
-    instance with the single-instance calls."""
+    instance with the single-instance calls.  Tables in the reduced form
+    (double-jump maps within a 40 GB budget, the rest chained), or no table
+    at all (table_free)."""
     import torch
     import paper_2005_13679_amd as mc
     from paper_2005_13679_amd import autotune
     from paper_2005_13679_amd.batch import Batch, BatchedLanczos, choose_double_jumps, plain_lanczos
     import workloads as W
     draws = W.batch_draws(64, 4)
-    use_t2 = choose_double_jumps(draws, budget_bytes=40e9, form="reduced")
+    use_t2 = ([False] * len(draws) if table_free
+              else choose_double_jumps(draws, budget_bytes=40e9, form="reduced"))
     insts = []
     for i, ((N, M), t2) in enumerate(zip(draws, use_t2)):
         _, h, g = W.random_instance(1, M, 1000 + i)
-        tab = mc.build_tables(N, M, dev, double_jumps=t2, form="reduced")
+        if table_free:
+            tab = mc.DirectSpace(N, M, dev)
+        else:
+            tab = mc.build_tables(N, M, dev, double_jumps=t2, form="reduced")
         insts.append((tab, torch.from_numpy(h).to(dev), torch.from_numpy(g).to(dev)))
     total_dim = sum(t.dim for t, _, _ in insts)
     print(f"[bench] batched: {len(insts)} instances, total dim {total_dim}; autotuning",
@@ -322,7 +328,9 @@ def batched_leg(dev, steps: int = 50) -> dict:
         if k > 0:
             worst = max(worst, float(np.max(np.abs(a_p[:k] - a_b[:k, i]) / np.maximum(1.0, np.abs(a_p[:k])))))
     t_plain = time.perf_counter() - t0
-    out = {"instances": len(insts), "total_dim": int(total_dim), "table_form": "reduced",
+    out = {"instances": len(insts), "total_dim": int(total_dim),
+           "table_form": "none (table-free)" if table_free else "reduced",
+           "table_bytes": int(sum(sum(t.nbytes().values()) for t, _, _ in insts)),
            "with_double_jump_map": int(sum(use_t2)), "steps": steps,
            "schedule": tuned["schedule"], "schedule_cached": tuned["cached"],
            "batched_apply_ms": apply_ms,
@@ -479,6 +487,8 @@ def main(argv=None):
         out["sil_step"] = sil_leg(dev)
         print("[bench] batched leg (64 instances, 50 Lanczos steps)", file=sys.stderr, flush=True)
         out["batched_vs_plain"] = batched_leg(dev)
+        print("[bench] batched leg, table-free instances", file=sys.stderr, flush=True)
+        out["batched_vs_plain_table_free"] = batched_leg(dev, table_free=True)
 
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a row sample", file=sys.stderr, flush=True)

@@ -9,6 +9,7 @@ arithmetic.  There is no CPU fallback.
 
 from ._lib import MCError, LIB_PATH
 from .api import (
+    DirectSpace,
     Tables,
     apply_H,
     apply_H_adjoint,
@@ -33,7 +34,7 @@ from .batch import Batch, BatchedLanczos, batched_lanczos
 from .propagate import SILStepper, sil_step
 
 __all__ = [
-    "MCError", "LIB_PATH", "SILStepper", "sil_step", "Batch", "BatchedLanczos", "batched_lanczos", "Energy", "Tables", "apply_H", "apply_H_adjoint", "apply_H_direct", "apply_H_sparse", "energy", "build_tables", "dim", "hash_batch",
+    "MCError", "LIB_PATH", "SILStepper", "sil_step", "Batch", "BatchedLanczos", "batched_lanczos", "Energy", "DirectSpace", "Tables", "apply_H", "apply_H_adjoint", "apply_H_direct", "apply_H_sparse", "energy", "build_tables", "dim", "hash_batch",
     "hash_occ", "rho1", "rho2", "t2_lookup", "tables_size", "unhash", "unhash_batch",
     "workspace_size", "zaxpby", "zdotc",
 ]

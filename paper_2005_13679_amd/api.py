@@ -190,6 +190,41 @@ def build_tables(N: int, M: int, device=None, double_jumps: bool = True,
 # operators
 # ---------------------------------------------------------------------------
 
+class DirectSpace:
+    """The space (N, M) with no table: ``apply_H`` on it evaluates H.C
+    table-free (mc_apply_H_direct), and as a batch item it runs table-free in
+    the persistent kernel.  ``c`` is a table descriptor holding sizes only."""
+
+    form = "direct"
+    t2 = None
+
+    def __init__(self, N: int, M: int, device=None):
+        device = torch.device(device if device is not None else "cuda")
+        if device.type != "cuda":
+            raise ValueError("the table-free apply runs on the GPU")
+        if device.index is None:
+            device = torch.device("cuda", torch.cuda.current_device())
+        self.N, self.M, self.device = int(N), int(M), device
+        self.dim = dim(N, M)
+        self.tiles = (self.dim + 63) // 64
+        c = L.CTables()
+        c.N, c.M, c.dim, c.tiles = self.N, self.M, self.dim, self.tiles
+        c.t2_required = -1
+        self.c = c
+        self._ws = None
+
+    def workspace(self, op: int) -> torch.Tensor:
+        if op != L.MC_OP_APPLY:
+            raise ValueError("a table-free space supports the H.C apply only")
+        if self._ws is None:
+            self._ws = torch.empty(max(16, workspace_size(self.N, self.M, op)), dtype=torch.uint8,
+                                   device=self.device)
+        return self._ws
+
+    def nbytes(self) -> dict:
+        return {}
+
+
 def _as_dev(x, device, shape=None) -> torch.Tensor:
     if not isinstance(x, torch.Tensor):
         x = torch.as_tensor(np.asarray(x))
@@ -199,8 +234,11 @@ def _as_dev(x, device, shape=None) -> torch.Tensor:
     return x.contiguous()
 
 
-def apply_H(h, g, C: torch.Tensor, tables: Tables, out: torch.Tensor | None = None) -> torch.Tensor:
-    """HC = H . C (Eq. Haction) on the GPU through the jump maps."""
+def apply_H(h, g, C: torch.Tensor, tables, out: torch.Tensor | None = None) -> torch.Tensor:
+    """HC = H . C (Eq. Haction) on the GPU through the jump maps (Tables), or
+    table-free (DirectSpace)."""
+    if isinstance(tables, DirectSpace):
+        return apply_H_direct(h, g, C, tables.N, tables.M, out=out, _space=tables)
     N, M, dev = tables.N, tables.M, tables.device
     h = _as_dev(h, dev, (M, M))
     g = _as_dev(g, dev, (M, M, M, M))
@@ -235,28 +273,30 @@ def apply_H_sparse(h, g, C: torch.Tensor, tables: Tables,
     return out
 
 
-_direct_ws: dict = {}
+_direct_spaces: dict = {}
 
 
 def apply_H_direct(h, g, C: torch.Tensor, N: int, M: int,
-                   out: torch.Tensor | None = None) -> torch.Tensor:
+                   out: torch.Tensor | None = None, _space: DirectSpace | None = None) -> torch.Tensor:
     """HC = H . C with no table: occupations and jump targets of every row
     from its index in closed form (M <= 8, dim < 2^31).  Device memory is C,
     out and a small workspace only."""
-    dev = C.device if isinstance(C, torch.Tensor) else torch.device("cuda")
-    D = dim(N, M)
+    if not isinstance(C, torch.Tensor):
+        raise TypeError("C must be a torch.Tensor")
+    dev = C.device
+    sp = _space
+    if sp is None:
+        sp = _direct_spaces.get((dev, N, M))
+        if sp is None:
+            sp = _direct_spaces[(dev, N, M)] = DirectSpace(N, M, dev)
+    D = sp.dim
     h = _as_dev(h, dev, (M, M))
     g = _as_dev(g, dev, (M, M, M, M))
     _require(C, "C", torch.complex128, dev, numel=D)
     if out is None:
         out = torch.empty_like(C)
     _require(out, "out", torch.complex128, dev, numel=D)
-    key = (dev, N, M)
-    ws = _direct_ws.get(key)
-    if ws is None:
-        ws = torch.empty(max(16, workspace_size(N, M, L.MC_OP_APPLY)), dtype=torch.uint8,
-                         device=dev)
-        _direct_ws[key] = ws
+    ws = sp.workspace(L.MC_OP_APPLY)
     with torch.cuda.device(dev):
         L.check(L.load().mc_apply_H_direct(N, M, _ptr(h), _ptr(g), _ptr(C), _ptr(out), _ptr(ws),
                                            ws.numel(), _stream(dev)), "mc_apply_H_direct")

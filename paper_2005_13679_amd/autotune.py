@@ -33,7 +33,7 @@ def default_cache_path() -> str:
 def signature(instances) -> str:
     dev = instances[0][0].device
     name = torch.cuda.get_device_name(dev)
-    shapes = sorted((t.N, t.M, t.t2 is not None) for t, _, _ in instances)
+    shapes = sorted((t.N, t.M, t.t2 is not None, t.form) for t, _, _ in instances)
     return hashlib.sha256(json.dumps([name, shapes]).encode()).hexdigest()[:24]
 
 

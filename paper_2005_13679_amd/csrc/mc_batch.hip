@@ -19,17 +19,18 @@
 
 #include "mc_apply.h"
 #include "mc_split.h"
+#include "mc_direct.h"
 #include "mc_internal.h"
 
 namespace mc {
 
 // How an instance's tile body runs: paper form through its map or chained,
 // case-split form through its reduced map or chained.
-enum BatchKind : int32_t { kPaperMap = 0, kPaperChain = 1, kSplitMap = 2, kSplitChain = 3 };
+enum BatchKind : int32_t { kPaperMap = 0, kPaperChain = 1, kSplitMap = 2, kSplitChain = 3, kDirect = 4 };
 
 struct BatchInst {
     int32_t N, M;
-    int32_t kind, pad;
+    int32_t kind, nbits;  // nbits: bit width of N (table-free kind)
     int64_t dim, tiles, cap, vec_off;
     const uint8_t *occ;
     const int32_t *t1;
@@ -60,7 +61,7 @@ struct BatchChunk {
 };
 
 constexpr int64_t kChunk = 1 << 16;
-constexpr int kMaxGroups = 32;   // 8 orbital counts x 4 kinds
+constexpr int kMaxGroups = 40;   // 8 orbital counts x 5 kinds
 constexpr int kGrab = 8;         // tiles a wavefront takes per counter increment (order 3)
 
 // An instance launched on a grid of its own; its tables are passed to the
@@ -81,12 +82,12 @@ struct SoloLaunch {
 struct mc_batch {
     int32_t count;
     int32_t ngroups;
-    int32_t group_M[32];
-    int32_t group_kind[32];   // BatchKind of the group's instances
-    int32_t group_first[32];  // first entry in the sorted instance order
-    int32_t group_count[32];
-    int64_t group_tiles[32];
-    int64_t group_blocks[32];
+    int32_t group_M[40];
+    int32_t group_kind[40];   // BatchKind of the group's instances
+    int32_t group_first[40];  // first entry in the sorted instance order
+    int32_t group_count[40];
+    int64_t group_tiles[40];
+    int64_t group_blocks[40];
     int64_t nchunks;
     int64_t total_len;        // batch-vector length
     int32_t order;
@@ -110,7 +111,7 @@ __global__ void k_batch_prep(const BatchInst *__restrict__ inst, uint32_t *__res
     const BatchInst I = inst[blockIdx.y];
     const int M = I.M;
     const int first = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
-    if (I.kind == kSplitMap || I.kind == kSplitChain) {
+    if (I.kind == kSplitMap || I.kind == kSplitChain || I.kind == kDirect) {
         stage_split_constants(M, 0, I.g, I.h, I.gp, first, stride);
         return;
     }
@@ -160,6 +161,8 @@ __device__ __forceinline__ void batch_tile(const BatchInst &I, int64_t tile, con
                                           gp, C, HC);
     else if constexpr (KIND == kPaperChain)
         apply_tile_chained<MT, uint8_t, false>(tile, I.dim, sq, occ, t1, hp, gp, C, HC);
+    else if constexpr (KIND == kDirect)
+        apply_tile_direct<MT, false>(tile, I.N, I.nbits, I.dim, sq, gp, C, HC);
     else
         apply_tile_split<MT, uint8_t, false, KIND == kSplitMap>(tile, I.dim, I.cap, sq, occ, t1,
                                                                 pmask, t2_off, t2, gp, C, HC);
@@ -235,7 +238,7 @@ void k_batch_apply(const BatchInst *__restrict__ inst, const int64_t *__restrict
 // instance's vector segments arrive as kernel arguments.
 template <int MT, int KIND>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MC_APPLY_WAVES)))
-void k_batch_solo(int64_t D, int64_t tiles, int64_t nblocks, int64_t cap,
+void k_batch_solo(int N, int nbits, int64_t D, int64_t tiles, int64_t nblocks, int64_t cap,
                   const uint8_t *__restrict__ occ, const int32_t *__restrict__ t1,
                   const uint64_t *__restrict__ pmask, const int64_t *__restrict__ t2_off,
                   const int32_t *__restrict__ t2, const double2 *__restrict__ gp,
@@ -251,6 +254,8 @@ void k_batch_solo(int64_t D, int64_t tiles, int64_t nblocks, int64_t cap,
                                           HC);
     else if constexpr (KIND == kPaperChain)
         apply_tile_chained<MT, uint8_t, false>(tile, D, sq, occ, t1, hp, gp, C, HC);
+    else if constexpr (KIND == kDirect)
+        apply_tile_direct<MT, false>(tile, N, nbits, D, sq, gp, C, HC);
     else
         apply_tile_split<MT, uint8_t, false, KIND == kSplitMap>(tile, D, cap, sq, occ, t1, pmask,
                                                                 t2_off, t2, gp, C, HC);
@@ -365,6 +370,12 @@ struct PlanLayout {
     size_t inst, prefix, chunks, partials, sorted, pos, counters, coef, total;
 };
 
+// An item whose descriptor holds sizes but no buffers runs table-free.
+static bool table_free(const mc_tables *t)
+{
+    return !t->binom_d && !t->occ_d && !t->t1_d && !t->pmask_d && !t->t2_off_d && !t->t2_d;
+}
+
 static int plan_layout(int32_t count, const mc_batch_item *items, int64_t *nchunks_out,
                        int64_t *coef_elems_out, PlanLayout *L)
 {
@@ -417,8 +428,14 @@ int mc_batch_create(int32_t count, const mc_batch_item *items, const mc_batch_sc
         if (!t || !items[i].h_d || !items[i].g_d) return MC_EINVAL;
         int st = check_nm(t->N, t->M);
         if (st) return st;
-        st = check_tables(t->N, t->M, t, t->t2_d != nullptr);
-        if (st) return st;
+        if (table_free(t)) {
+            // sizes only: they must be those of (N, M)
+            const int64_t D = dim_checked(t->N, t->M);
+            if (D < 0 || t->dim != D || t->tiles != (D + kTile - 1) / kTile) return MC_EINVAL;
+        } else {
+            st = check_tables(t->N, t->M, t, t->t2_d != nullptr);
+            if (st) return st;
+        }
         // batched instances: M <= 8, N <= 255, D < 2^28 (range-checked gathers)
         if (t->M > 8 || occ_width(t->N) != 1 || t->dim * 16 > (int64_t)0xFFFFFFFFu) return MC_EINVAL;
     }
@@ -433,6 +450,7 @@ int mc_batch_create(int32_t count, const mc_batch_item *items, const mc_batch_sc
 
     // instance order: by orbital count, then kind, then decreasing dimension
     auto kind_of = [](const mc_tables *t) -> int32_t {
+        if (table_free(t)) return kDirect;
         const bool split = t->form == MC_FORM_REDUCED, map = t->t2_d != nullptr;
         return split ? (map ? kSplitMap : kSplitChain) : (map ? kPaperMap : kPaperChain);
     };
@@ -470,7 +488,7 @@ int mc_batch_create(int32_t count, const mc_batch_item *items, const mc_batch_sc
         I.N = t->N;
         I.M = t->M;
         I.kind = kind_of(t);
-        I.pad = 0;
+        I.nbits = bit_width(t->N);
         I.dim = t->dim;
         I.tiles = t->tiles;
         I.cap = t->t2_d ? t->t2_entries : 0;
@@ -609,7 +627,8 @@ int mc_batch_apply_H(const mc_batch *b, const double *C_d, double *HC_d, mc_stre
         const int M = L1.M;
         const int64_t nblocks = (L1.tiles + 3) / 4;
 #define MC_SOLO_LAUNCH(KIND)                                                                    \
-    hipLaunchKernelGGL((k_batch_solo<MT, KIND>), dim3(nblocks), dim3(256), 0, s, L1.dim,         \
+    hipLaunchKernelGGL((k_batch_solo<MT, KIND>), dim3(nblocks), dim3(256), 0, s, L1.N,           \
+                       bit_width(L1.N), L1.dim,                                                  \
                        L1.tiles, nblocks, L1.cap, L1.occ, L1.t1, L1.pmask, L1.t2_off, L1.t2,     \
                        (const double2 *)b->coef_d + L1.gp_off,                                   \
                        (const double2 *)b->coef_d + L1.hp_off,                                   \
@@ -618,6 +637,7 @@ int mc_batch_apply_H(const mc_batch *b, const double *C_d, double *HC_d, mc_stre
         case kPaperMap: MC_DISPATCH_M(M, if constexpr (MT > 0) MC_SOLO_LAUNCH(kPaperMap)); break;
         case kPaperChain: MC_DISPATCH_M(M, if constexpr (MT > 0) MC_SOLO_LAUNCH(kPaperChain)); break;
         case kSplitMap: MC_DISPATCH_M(M, if constexpr (MT > 0) MC_SOLO_LAUNCH(kSplitMap)); break;
+        case kDirect: MC_DISPATCH_M(M, if constexpr (MT > 0) MC_SOLO_LAUNCH(kDirect)); break;
         default: MC_DISPATCH_M(M, if constexpr (MT > 0) MC_SOLO_LAUNCH(kSplitChain)); break;
         }
 #undef MC_SOLO_LAUNCH
@@ -633,6 +653,7 @@ int mc_batch_apply_H(const mc_batch *b, const double *C_d, double *HC_d, mc_stre
         case kPaperMap: MC_DISPATCH_M(M, if constexpr (MT > 0) MC_BATCH_LAUNCH(kPaperMap)); break;
         case kPaperChain: MC_DISPATCH_M(M, if constexpr (MT > 0) MC_BATCH_LAUNCH(kPaperChain)); break;
         case kSplitMap: MC_DISPATCH_M(M, if constexpr (MT > 0) MC_BATCH_LAUNCH(kSplitMap)); break;
+        case kDirect: MC_DISPATCH_M(M, if constexpr (MT > 0) MC_BATCH_LAUNCH(kDirect)); break;
         default: MC_DISPATCH_M(M, if constexpr (MT > 0) MC_BATCH_LAUNCH(kSplitChain)); break;
         }
 #undef MC_BATCH_LAUNCH

@@ -34,6 +34,13 @@ int launch_status();                   // hipGetLastError -> status
 inline int npairs(int M) { return M * (M + 1) / 2; }
 inline int pair_words(int M) { return (npairs(M) + 63) / 64; }
 inline int occ_width(int N) { return N <= 255 ? 1 : 2; }
+// number of bits of N (N >= 0)
+inline int bit_width(int N)
+{
+    int b = 0;
+    while (b < 31 && (1 << b) <= N) ++b;
+    return b;
+}
 // Slots of removal pair (k, s) in the reduced double-jump map: creation
 // pairs q <= l with q, l outside {k, s}.
 __host__ __device__ constexpr int reduced_slots(int M, int k, int s)

@@ -1124,8 +1124,7 @@ int mc_apply_H_direct(int32_t N, int32_t M, const double *h_d, const double *g_d
                        (const double2 *)h_d, cf);
     const int64_t tiles = (D + kTile - 1) / kTile;
     const int64_t nblocks = (tiles + 3) / 4;
-    int nbits = 0;
-    while ((1 << nbits) <= N) ++nbits;   // bit width of N
+    const int nbits = bit_width(N);
     const bool big = D * 16 > (int64_t)0xFFFFFFFFu;
     MC_DISPATCH_M(M, if constexpr (MT > 0 && MT <= 8) {
         if (big)

@@ -17,7 +17,10 @@ SHAPES = [(8, 3, True, "paper"), (12, 4, False, "paper"), (3, 8, True, "paper"),
           (15, 6, False, "paper"), (8, 8, False, "paper"), (5, 7, False, "paper"),
           (4, 8, True, "paper"), (11, 5, True, "reduced"), (9, 4, False, "reduced"),
           (6, 8, False, "reduced"), (5, 7, True, "reduced"), (2, 2, True, "reduced"),
-          (3, 1, False, "reduced"), (12, 6, False, "reduced")]
+          (3, 1, False, "reduced"), (12, 6, False, "reduced"),
+          # table-free instances (descriptors with sizes only)
+          (7, 5, False, "direct"), (10, 3, False, "direct"), (4, 8, False, "direct"),
+          (14, 6, False, "direct"), (1, 2, False, "direct"), (9, 7, False, "direct")]
 
 
 def dev(x):
@@ -30,7 +33,10 @@ def small_batch(mc):
     insts, host = [], []
     for i, (N, M, t2, form) in enumerate(SHAPES):
         C, h, g = W.random_instance(N, M, 100 + i)
-        tab = mc.build_tables(N, M, double_jumps=t2, form=form)
+        if form == "direct":
+            tab = mc.DirectSpace(N, M)
+        else:
+            tab = mc.build_tables(N, M, double_jumps=t2, form=form)
         insts.append((tab, dev(h), dev(g)))
         host.append((N, M, C, h, g))
     return insts, host
@@ -137,6 +143,34 @@ def test_autotuner_caches(mc, small_batch, tmp_path):
     assert not r1["cached"] and r1["schedule"] in autotune.CANDIDATES[:3]
     r2 = autotune.tune(insts, cache_path=path)
     assert r2["cached"] and r2["schedule"] == r1["schedule"]
+
+
+def test_table_free_batch_of_large_instances(mc, oracle_native):
+    """Table-free instances, some large enough for launches of their own
+    (N = 40, M = 8: dim 62,891,499 is the largest draw of the 64-instance
+    workload), against the plain table-free apply; sampled rows vs the oracle."""
+    from paper_2005_13679_amd.batch import Batch
+    shapes = [(40, 8), (30, 6), (12, 7), (25, 4), (8, 3)]
+    insts, host = [], []
+    for i, (N, M) in enumerate(shapes):
+        _, h, g = W.random_instance(1, M, 500 + i)
+        insts.append((mc.DirectSpace(N, M), dev(h), dev(g)))
+        host.append((N, M, h, g))
+    b = Batch(insts, {"blocks_per_cu": 2, "order": 3, "solo_tiles": 16384})
+    rng = np.random.default_rng(77)
+    C = b.vector()
+    C.copy_(torch.complex(torch.randn(b.length, dtype=torch.float64, device="cuda"),
+                          torch.randn(b.length, dtype=torch.float64, device="cuda")))
+    HC = b.apply_H(C, b.vector())
+    for i, ((sp, hd, gd), (N, M, h, g)) in enumerate(zip(insts, host)):
+        Ci = b.segment(C, i).contiguous()
+        plain = mc.apply_H(hd, gd, Ci, sp)
+        assert torch.equal(b.segment(HC, i), plain), (N, M)
+        rows = np.unique(np.concatenate([rng.integers(0, sp.dim, 300), [0, sp.dim - 1]]))
+        ref = oracle_native.apply_h(N, M, h, g, Ci.cpu().numpy(), rows)
+        assert rel_inf(plain[torch.from_numpy(rows).cuda()].cpu().numpy(), ref) <= 1e-12
+    del b, C, HC
+    torch.cuda.empty_cache()
 
 
 def test_batch_rejects_unsupported(mc):
