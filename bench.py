@@ -83,9 +83,19 @@ def algorithmic_bytes(N: int, M: int, path: str = "reduced_map") -> dict:
     return parts
 
 
-def kernel_source_hash() -> str:
+# sources each path's apply kernel is built from
+KERNEL_SOURCES = {
+    "reduced_map": ("mc_ops.hip", "mc_internal.h", "mc_apply.h", "mc_split.h"),
+    "reduced_chained": ("mc_ops.hip", "mc_internal.h", "mc_apply.h", "mc_split.h"),
+    "paper_map": ("mc_ops.hip", "mc_internal.h", "mc_apply.h"),
+    "paper_chained": ("mc_ops.hip", "mc_internal.h", "mc_apply.h"),
+    "direct": ("mc_ops.hip", "mc_internal.h", "mc_apply.h", "mc_split.h", "mc_direct.h"),
+}
+
+
+def kernel_source_hash(path: str = "reduced_map") -> str:
     h = hashlib.sha256()
-    for f in ("mc_ops.hip", "mc_internal.h", "mc_apply.h", "mc_split.h", "mc_direct.h"):
+    for f in KERNEL_SOURCES[path]:
         with open(os.path.join(ROOT, "paper_2005_13679_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -99,7 +109,7 @@ def measured_traffic(N: int, M: int, path_name: str):
         return None
     with open(path) as f:
         d = json.load(f)
-    if d.get("kernel_source_hash") != kernel_source_hash():
+    if d.get("kernel_source_hash") != kernel_source_hash(path_name):
         return None
     return d.get("hbm_bytes_per_launch")
 

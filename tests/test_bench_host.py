@@ -33,3 +33,13 @@ def test_byte_models():
     direct = bench.algorithmic_bytes(N, M, "direct")
     assert direct["total"] == 32 * D                   # no table: C in, HC out
     assert set(bench.PATHS) == set(bench.KERNELS)
+
+
+def test_counter_records_follow_their_kernel_sources():
+    sys.path.insert(0, ROOT)
+    import bench
+    assert set(bench.KERNEL_SOURCES) == set(bench.PATHS)
+    for p in bench.PATHS:
+        assert len(bench.kernel_source_hash(p)) == 16
+    # a table-free source change leaves the table paths' records valid
+    assert "mc_direct.h" not in bench.KERNEL_SOURCES["reduced_map"]
