@@ -215,7 +215,20 @@ def sil_leg(dev, N: int = 200, M: int = 5, dt: float = 1e-5, tol: float = 1e-10)
     res = {"workload": f"N={N}, M={M}, dim {C.size}, reduced tables", "dt": dt, "tol": tol,
            "krylov_dim": m, "error_estimate": err, "step_ms": sec * 1e3,
            "ms_per_krylov_vector": sec * 1e3 / max(m, 1)}
-    del st, tab, out, Cd
+    del st, tab
+    torch.cuda.empty_cache()
+    # the same step with no table
+    st = mc.SILStepper(mc.DirectSpace(N, M, dev), hd, gd, kmax=16)
+    out2 = torch.empty_like(Cd)
+    st.step(Cd, dt, tol=tol, out=out2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out2, m2, _ = st.step(Cd, dt, tol=tol, out=out2)
+    torch.cuda.synchronize()
+    sec2 = time.perf_counter() - t0
+    res["table_free"] = {"krylov_dim": m2, "step_ms": sec2 * 1e3,
+                         "same_result": bool(torch.equal(out, out2))}
+    del st, out, out2, Cd
     torch.cuda.empty_cache()
     return res
 

@@ -247,7 +247,8 @@ void k_batch_solo(int N, int nbits, int64_t D, int64_t tiles, int64_t nblocks, i
 {
     __shared__ double sq[kLdsRoots<MT> ? kBatchMaxN + 3 : 1];
     if constexpr (kLdsRoots<MT>) fill_sqrt_table(sq, kBatchMaxN + 3);
-    const int64_t tile = xcd_block(blockIdx.x, nblocks) * 4 + wave_in_block();
+    const int64_t tile =
+        xcd_block_as<KIND == kDirect && kDirectRemap<MT>>(blockIdx.x, nblocks) * 4 + wave_in_block();
     if (tile >= tiles) return;
     if constexpr (KIND == kPaperMap)
         apply_tile_t2<MT, uint8_t, false>(tile, D, cap, sq, occ, t1, pmask, t2_off, t2, hp, gp, C,

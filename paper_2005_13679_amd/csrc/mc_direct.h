@@ -150,14 +150,32 @@ __device__ __forceinline__ int32_t direct_target(const DirectRow<MT> &row, const
     }
 }
 
+// Gathers per basic block (MC_DIRECT_BATCH_WIDE from M = MC_DIRECT_WIDE_FROM
+// on, where a tile's 869 windows overrun the caches), and from which M on the
+// launch maps blocks to XCD-contiguous ranges of tiles (the L2 of each XCD
+// then serves the windows of its own range; measured 6-12 % faster at
+// M = 6, 7 and, with the smaller batch, 16 % at M = 8; 1 % slower at M = 5).
 #ifndef MC_DIRECT_BATCH
 #define MC_DIRECT_BATCH 16
 #endif
+#ifndef MC_DIRECT_BATCH_WIDE
+#define MC_DIRECT_BATCH_WIDE 12
+#endif
+#ifndef MC_DIRECT_WIDE_FROM
+#define MC_DIRECT_WIDE_FROM 8
+#endif
+#ifndef MC_DIRECT_REMAP_FROM
+#define MC_DIRECT_REMAP_FROM 6
+#endif
+
+template <int MT>
+constexpr bool kDirectRemap = MT >= MC_DIRECT_REMAP_FROM;
 
 template <int MT>
 struct DirectStream {
     static constexpr int U = FlatTile<MT>::U;
-    static constexpr int SB = U < MC_DIRECT_BATCH ? (U > 0 ? U : 1) : MC_DIRECT_BATCH;
+    static constexpr int B = MT >= MC_DIRECT_WIDE_FROM ? MC_DIRECT_BATCH_WIDE : MC_DIRECT_BATCH;
+    static constexpr int SB = U < B ? (U > 0 ? U : 1) : B;
     static constexpr int NB = (U + SB - 1) / SB;
 };
 

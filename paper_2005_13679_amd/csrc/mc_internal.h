@@ -214,6 +214,17 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb)
     return xcd * per + (xcd < rem ? xcd : rem) + local;
 }
 
+// The same with the mapping chosen per kernel: XCD-contiguous ranges (REMAP)
+// or the build default.
+template <bool REMAP>
+__device__ __forceinline__ int64_t xcd_block_as(int64_t b, int64_t nb)
+{
+    if constexpr (!REMAP) return xcd_block(b, nb);
+    const int64_t xcd = b & 7, local = b >> 3;
+    const int64_t per = nb >> 3, rem = nb & 7;
+    return xcd * per + (xcd < rem ? xcd : rem) + local;
+}
+
 }  // namespace mc
 
 // Dispatch a templated kernel launch on a compile-time orbital count for

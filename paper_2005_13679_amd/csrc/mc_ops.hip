@@ -117,7 +117,7 @@ void k_apply_direct(int N, int nbits, int64_t D, int64_t tiles, int64_t nblocks,
 {
     extern __shared__ double sq[];
     if constexpr (kLdsRoots<MT>) fill_sqrt_table(sq, N + 3);
-    const int64_t tile = xcd_block(blockIdx.x, nblocks) * 4 + wave_in_block();
+    const int64_t tile = xcd_block_as<kDirectRemap<MT>>(blockIdx.x, nblocks) * 4 + wave_in_block();
     if (tile >= tiles) return;
     apply_tile_direct<MT, BIGC>(tile, N, nbits, D, sq, cf, C, HC);
 }

@@ -100,3 +100,36 @@ def test_direct_rejects_bad_sizes(mc):
     C = z(mc.dim(4, 3))
     with pytest.raises(mc.MCError):            # output aliases the input
         mc.apply_H_direct(z(3, 3), z(3, 3, 3, 3), C, 4, 3, out=C)
+
+
+@pytest.mark.parametrize("N,M,seed,k", [(10, 5, 0, 12), (6, 8, 7, 6), (20, 3, 6, 8)])
+def test_direct_sil_step_matches_oracle(mc, oracle_native, N, M, seed, k):
+    """A SIL step on a table-free space (DirectSpace): same result as on
+    reduced tables, and the oracle's SIL step within 1e-11 (k Krylov steps
+    at the 1e-12 apply bar)."""
+    from oracle import propagate as pr
+    C, h, g = W.random_instance(N, M, seed)
+    ref, m_ref, _ = pr.sil_step(lambda v: oracle_native.apply_h(N, M, h, g, v), C, 0.02, k=k)
+    got, m, _ = mc.sil_step(mc.DirectSpace(N, M), dev(h), dev(g), dev(C), 0.02, k=k)
+    tab, m2, _ = mc.sil_step(mc.build_tables(N, M, form="reduced"), dev(h), dev(g), dev(C), 0.02, k=k)
+    assert m == m_ref == m2
+    assert rel_inf(got.cpu().numpy(), ref) <= 1e-11
+    assert torch.equal(got, tab)
+
+
+def test_direct_lanczos_lieb_liniger_energies(mc):
+    """Lanczos ground states of the plane-wave Lieb-Liniger ring on table-free
+    spaces equal the oracle's stored energies (N = 20, M up to 7)."""
+    import json
+    import os
+    from paper_2005_13679_amd import lanczos
+    from tests.conftest import ROOT
+    ref = json.load(open(os.path.join(ROOT, "tests", "golden", "ll_energies.json")))
+    N, L = ref["N"], ref["L"]
+    for r in ref["runs"]:
+        M = r["M"]
+        h, g = W.lieb_liniger_h(M, L), W.lieb_liniger_g(M, r["c"], L)
+        sp = mc.DirectSpace(N, M)
+        v0 = W.random_coefficients(np.random.default_rng(1000 + M), sp.dim)
+        e, *_ = lanczos.ground_state(h, g, sp, dev(v0), max_iter=400, tol=1e-13)
+        assert abs(e - r["E0"]) <= 1e-9 * abs(r["E0"]), (r, e)
