@@ -133,3 +133,39 @@ def test_direct_lanczos_lieb_liniger_energies(mc):
         v0 = W.random_coefficients(np.random.default_rng(1000 + M), sp.dim)
         e, *_ = lanczos.ground_state(h, g, sp, dev(v0), max_iter=400, tol=1e-13)
         assert abs(e - r["E0"]) <= 1e-9 * abs(r["E0"]), (r, e)
+
+
+@pytest.mark.timeout(600)
+def test_direct_maximum_dimension(mc, oracle_native):
+    """N = 473, M = 5: dim 2,130,031,575, the largest below 2^31 (the tables
+    would need 213 GB for the single-jump map alone).  C is a closed-form
+    function of the index, made on the device and copied to the host for the
+    oracle; sampled rows against the oracle, the extreme rows included, and
+    Hermiticity <D|HC> = conj<C|HD> over the whole space."""
+    N, M = 473, 5
+    D = oracle_native.dim(N, M)
+    assert D == 2130031575 and D < 2 ** 31
+    _, h, g = W.random_instance(1, M, 41)              # Hermitian h, symmetric g
+    k = torch.arange(D, dtype=torch.float64, device="cuda")
+    Cd = torch.complex(torch.cos(0.3718 * k), torch.sin(0.9127 * k + 0.25))
+    del k
+    C = Cd.cpu().numpy()
+    hd, gd = dev(h), dev(g)
+    hc = mc.apply_H_direct(hd, gd, Cd, N, M)
+    rng = np.random.default_rng(43)
+    rows = np.unique(np.concatenate([rng.integers(0, D, 600), np.arange(64), D - 1 - np.arange(64)]))
+    ref = oracle_native.apply_h(N, M, h, g, C, rows)
+    got = hc[torch.from_numpy(rows).cuda()].cpu().numpy()
+    assert rel_inf(got, ref) <= TOL
+    del C
+    # Hermiticity with a second vector made on the device
+    k = torch.arange(D, dtype=torch.float64, device="cuda")
+    Dv = torch.complex(torch.sin(0.113 * k), torch.cos(0.271 * k))
+    del k
+    hd_v = mc.apply_H_direct(hd, gd, Dv, N, M)
+    lhs = mc.zdotc(Dv, hc).item()
+    rhs = mc.zdotc(Cd, hd_v).item()
+    bound = (mc.zdotc(Dv, Dv).item().real * mc.zdotc(hc, hc).item().real) ** 0.5
+    assert abs(lhs - rhs.conjugate()) <= 1e-11 * bound
+    del Cd, hc, Dv, hd_v
+    torch.cuda.empty_cache()
