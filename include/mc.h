@@ -261,7 +261,8 @@ int mc_apply_H_sparse(int32_t N, int32_t M, const double *h_d, const double *g_d
  * differences (the O(M) index delta; Sec. III, IV).  Needs no mc_tables:
  * device memory is C_d, HC_d and the workspace only, which lifts the table
  * memory limit on N.  1 <= M <= 8 and D < 2^31 (else MC_EINVAL / MC_ERANGE),
- * (N+3)*8 <= 65536; ws_d: mc_workspace_size(APPLY) bytes (staged constants,
+ * (N+3)*8 <= 65536 for M >= 6 (an LDS table of square roots; M <= 5 keeps
+ * them in registers); ws_d: mc_workspace_size(APPLY) bytes (staged constants,
  * so concurrent calls need separate ws); HC_d must not overlap C_d.  The
  * terms and their order are those of mc_apply_H on reduced-form tables, so
  * the results agree with it up to the sign of zero. */
@@ -324,7 +325,10 @@ int mc_zaxpby(int64_t n, const double *a_d, const double *x_d, const double *b_d
  * calls on one stream are ordered.
  */
 typedef struct mc_batch_item {
-    const mc_tables *tables;     /* host pointer to built tables of the instance */
+    const mc_tables *tables;     /* host pointer to built tables of the instance, or to a
+                                    descriptor with N, M, dim, tiles set and every buffer
+                                    pointer NULL: the instance then runs table-free (the
+                                    evaluation of mc_apply_H_direct) */
     const double *h_d, *g_d;     /* h [M*M], g [M^4] complex128, device; read at each apply */
 } mc_batch_item;
 

@@ -1117,7 +1117,7 @@ int mc_apply_H_direct(int32_t N, int32_t M, const double *h_d, const double *g_d
     mc_workspace_size(N, M, MC_OP_APPLY, &need);
     if (ws_bytes < need) return MC_ENOMEM;
     const size_t sqb = (size_t)(N + 3) * 8;
-    if (sqb > 65536) return MC_EINVAL;
+    if (M >= MC_LDS_ROOTS_FROM && sqb > 65536) return MC_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     double2 *cf = (double2 *)ws_d;
     hipLaunchKernelGGL(k_prep_split, dim3(4), dim3(256), 0, s, M, 0, (const double2 *)g_d,

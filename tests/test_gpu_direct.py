@@ -93,6 +93,20 @@ def test_direct_64bit_gathers_sampled_rows(mc, oracle_native):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("N,M", [(65535, 2), (9000, 3), (600, 4)])
+def test_direct_large_N_few_orbitals(mc, oracle_native, N, M):
+    """N up to MC_MAX_N at few orbitals (no square-root table in LDS below
+    M = 6, so N is bounded only by D < 2^31); sampled rows vs the oracle."""
+    rng = np.random.default_rng(N + M)
+    D = oracle_native.dim(N, M)
+    C = W.random_coefficients(rng, D)
+    _, h, g = W.random_instance(1, M, 60 + M)
+    hc = mc.apply_H_direct(dev(h), dev(g), dev(C), N, M)
+    rows = np.unique(np.concatenate([rng.integers(0, D, 300), np.arange(64), D - 1 - np.arange(64)]))
+    got = hc[torch.from_numpy(rows).cuda()].cpu().numpy()
+    assert rel_inf(got, oracle_native.apply_h(N, M, h, g, C, rows)) <= TOL
+
+
 def test_direct_rejects_bad_sizes(mc):
     z = lambda *s: torch.zeros(s, dtype=torch.complex128, device="cuda")
     with pytest.raises(mc.MCError):            # M > 8
