@@ -215,7 +215,8 @@ class DirectSpace:
 
     def workspace(self, op: int) -> torch.Tensor:
         if op != L.MC_OP_APPLY:
-            raise ValueError("a table-free space supports the H.C apply only")
+            raise ValueError("a table-free space supports the H.C apply only; the density "
+                             "matrices need tables (build_tables)")
         if self._ws is None:
             self._ws = torch.empty(max(16, workspace_size(self.N, self.M, op)), dtype=torch.uint8,
                                    device=self.device)
@@ -306,6 +307,9 @@ def apply_H_direct(h, g, C: torch.Tensor, N: int, M: int,
 def apply_H_adjoint(h, g, C: torch.Tensor, tables: Tables,
                     out: torch.Tensor | None = None) -> torch.Tensor:
     """H^dagger . C (h -> h^dagger, g_ksql -> conj(g_lqsk))."""
+    if isinstance(tables, DirectSpace):
+        raise ValueError("the adjoint apply needs tables (for Hermitian h and g, "
+                         "H^dagger C = H C: use apply_H)")
     N, M, dev = tables.N, tables.M, tables.device
     h = _as_dev(h, dev, (M, M))
     g = _as_dev(g, dev, (M, M, M, M))

@@ -183,3 +183,23 @@ def test_direct_maximum_dimension(mc, oracle_native):
     assert abs(lhs - rhs.conjugate()) <= 1e-11 * bound
     del Cd, hc, Dv, hd_v
     torch.cuda.empty_cache()
+
+
+def test_direct_energy_gradient_in_C(mc):
+    """E = <C|HC> on a table-free space: value and dE/dC (Hermitian h, g)
+    equal those on reduced tables; the h and g gradients, which need the
+    density matrices, raise a clear error."""
+    N, M = 12, 5
+    C, h, g = W.random_instance(N, M, 71)
+    out = []
+    for space in (mc.DirectSpace(N, M), mc.build_tables(N, M, form="reduced")):
+        Ct = dev(C).requires_grad_(True)
+        E = mc.energy(Ct, dev(h), dev(g), space)
+        E.real.backward()
+        out.append((E.detach(), Ct.grad))
+    assert torch.equal(out[0][0], out[1][0])
+    assert torch.equal(out[0][1], out[1][1])
+    hg = dev(h).requires_grad_(True)
+    E = mc.energy(dev(C), hg, dev(g), mc.DirectSpace(N, M))
+    with pytest.raises(ValueError):
+        E.real.backward()
