@@ -283,6 +283,21 @@ int mc_rho1(int32_t N, int32_t M, const mc_tables *t, const double *C_d,
 int mc_rho2(int32_t N, int32_t M, const mc_tables *t, const double *C_d,
             double *rho2_d, void *ws_d, size_t ws_bytes, mc_stream stream);
 
+/* rho1_d [M*M] (Eq. rho1) and rho2_d [M^4] (Eq. rho2) with no table: each
+ * row's occupations and each target configuration computed from the row
+ * index in closed form, as in mc_apply_H_direct (a creation into a removed
+ * orbital cancels in the closed form, so the coincident-index slots of
+ * rho2 need no case analysis; App. B).  rho2 is accumulated over unordered
+ * removal pairs and expanded with rho2_ksql = rho2_skql.  1 <= M <= 8,
+ * D < 2^31 (MC_ERANGE), (N+3)*8 <= 65536; rho2 also needs 16 D <= 2^32.
+ * ws_d: mc_workspace_size(RHO1 / RHO2) bytes (per-wavefront partials,
+ * summed in a fixed order: bitwise reproducible).  Results equal mc_rho1 /
+ * mc_rho2 up to rounding order. */
+int mc_rho1_direct(int32_t N, int32_t M, const double *C_d, double *rho1_d, void *ws_d,
+                   size_t ws_bytes, mc_stream stream);
+int mc_rho2_direct(int32_t N, int32_t M, const double *C_d, double *rho2_d, void *ws_d,
+                   size_t ws_bytes, mc_stream stream);
+
 /* out_d[1] complex = sum_i conj(x_i) y_i over n elements, fixed-order
  * reduction in ws_d (mc_workspace_size(DOT) for n = D of (N, M), or any
  * ws of at least 16 * MC_DOT_BLOCKS + 16 bytes). */

@@ -214,13 +214,16 @@ class DirectSpace:
         self._ws = None
 
     def workspace(self, op: int) -> torch.Tensor:
-        if op != L.MC_OP_APPLY:
-            raise ValueError("a table-free space supports the H.C apply only; the density "
-                             "matrices need tables (build_tables)")
+        if op not in (L.MC_OP_APPLY, L.MC_OP_RHO1, L.MC_OP_RHO2):
+            raise ValueError("a table-free space supports H.C, rho1 and rho2")
         if self._ws is None:
-            self._ws = torch.empty(max(16, workspace_size(self.N, self.M, op)), dtype=torch.uint8,
-                                   device=self.device)
-        return self._ws
+            self._ws = {}
+        ws = self._ws.get(op)
+        if ws is None:
+            ws = torch.empty(max(16, workspace_size(self.N, self.M, op)), dtype=torch.uint8,
+                             device=self.device)
+            self._ws[op] = ws
+        return ws
 
     def nbytes(self) -> dict:
         return {}
@@ -351,13 +354,19 @@ def zaxpby(x: torch.Tensor, a: torch.Tensor | None = None, y: torch.Tensor | Non
 
 
 def rho1(C: torch.Tensor, tables: Tables, out: torch.Tensor | None = None) -> torch.Tensor:
-    """One-body reduced density matrix rho_kl = <a+_k a_l> (Eq. rho1)."""
+    """One-body reduced density matrix rho_kl = <a+_k a_l> (Eq. rho1), through
+    the single-jump map (Tables) or table-free (DirectSpace)."""
     M, dev = tables.M, tables.device
     _require(C, "C", torch.complex128, dev, numel=tables.dim)
     if out is None:
         out = torch.empty((M, M), dtype=torch.complex128, device=dev)
     _require(out, "out", torch.complex128, dev, numel=M * M)
     ws = tables.workspace(L.MC_OP_RHO1)
+    if isinstance(tables, DirectSpace):
+        with torch.cuda.device(dev):
+            L.check(L.load().mc_rho1_direct(tables.N, M, _ptr(C), _ptr(out), _ptr(ws), ws.numel(),
+                                            _stream(dev)), "mc_rho1_direct")
+        return out
     with torch.cuda.device(dev):
         L.check(L.load().mc_rho1(tables.N, M, ctypes.byref(tables.c), _ptr(C), _ptr(out),
                                  _ptr(ws), ws.numel(), _stream(dev)), "mc_rho1")
@@ -365,13 +374,19 @@ def rho1(C: torch.Tensor, tables: Tables, out: torch.Tensor | None = None) -> to
 
 
 def rho2(C: torch.Tensor, tables: Tables, out: torch.Tensor | None = None) -> torch.Tensor:
-    """Two-body reduced density matrix rho_ksql = <a+_k a+_s a_q a_l> (Eq. rho2)."""
+    """Two-body reduced density matrix rho_ksql = <a+_k a+_s a_q a_l> (Eq. rho2),
+    through the double-jump map (Tables) or table-free (DirectSpace)."""
     M, dev = tables.M, tables.device
     _require(C, "C", torch.complex128, dev, numel=tables.dim)
     if out is None:
         out = torch.empty((M, M, M, M), dtype=torch.complex128, device=dev)
     _require(out, "out", torch.complex128, dev, numel=M ** 4)
     ws = tables.workspace(L.MC_OP_RHO2)
+    if isinstance(tables, DirectSpace):
+        with torch.cuda.device(dev):
+            L.check(L.load().mc_rho2_direct(tables.N, M, _ptr(C), _ptr(out), _ptr(ws), ws.numel(),
+                                            _stream(dev)), "mc_rho2_direct")
+        return out
     with torch.cuda.device(dev):
         L.check(L.load().mc_rho2(tables.N, M, ctypes.byref(tables.c), _ptr(C), _ptr(out),
                                  _ptr(ws), ws.numel(), _stream(dev)), "mc_rho2")

@@ -181,6 +181,10 @@ def test_device_entry_points_reject_bad_arguments_before_launch(lib):
     assert lib.mc_apply_H_direct(10, 9, None, None, None, None, None, 0, None) == -1
     assert lib.mc_apply_H_direct(600, 5, None, None, None, None, None, 0, None) == -2
     assert lib.mc_apply_H_direct(10, 5, None, None, None, None, None, 0, None) == -1
+    for f in (lib.mc_rho1_direct, lib.mc_rho2_direct):
+        assert f(10, 9, None, None, None, 0, None) == -1
+        assert f(600, 5, None, None, None, 0, None) == -2
+        assert f(10, 5, None, None, None, 0, None) == -1
 
 
 @pytest.mark.parametrize("K", [1, 2, 3, 7, 20, 40])

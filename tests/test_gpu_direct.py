@@ -185,21 +185,51 @@ def test_direct_maximum_dimension(mc, oracle_native):
     torch.cuda.empty_cache()
 
 
-def test_direct_energy_gradient_in_C(mc):
-    """E = <C|HC> on a table-free space: value and dE/dC (Hermitian h, g)
-    equal those on reduced tables; the h and g gradients, which need the
-    density matrices, raise a clear error."""
+@pytest.mark.parametrize("N,M,seed", [(1, 1, 0), (3, 1, 1), (1, 4, 2), (2, 2, 3), (10, 5, 0),
+                                      (7, 4, 5), (5, 7, 6), (6, 8, 7), (12, 6, 8), (300, 2, 12),
+                                      (40, 3, 9), (2, 3, 15)])
+def test_direct_density_matrices_match_oracle(mc, oracle_native, N, M, seed):
+    C, h, g = W.random_instance(N, M, seed)
+    sp = mc.DirectSpace(N, M)
+    r1 = mc.rho1(dev(C), sp).cpu().numpy()
+    r2 = mc.rho2(dev(C), sp).cpu().numpy()
+    assert rel_inf(r1, oracle_native.rho1(N, M, C)) <= TOL
+    assert rel_inf(r2, oracle_native.rho2(N, M, C)) <= TOL
+
+
+def test_direct_density_matrices_match_tables(mc):
+    """N = 30, M = 6 (dim 324,632): table-free rho1, rho2 against the
+    table-driven kernels (different summation order, same sums)."""
+    N, M = 30, 6
+    C, _, _ = W.random_instance(N, M, 19)
+    sp, tab = mc.DirectSpace(N, M), mc.build_tables(N, M)
+    for f in (mc.rho1, mc.rho2):
+        assert rel_inf(f(dev(C), sp).cpu().numpy(), f(dev(C), tab).cpu().numpy()) <= TOL
+
+
+def test_direct_energy_gradients(mc):
+    """E = <C|HC> on a table-free space: value and every gradient (C, h, g)
+    against the reduced-table run; the non-Hermitian C-gradient needs the
+    adjoint apply, which needs tables, and says so."""
     N, M = 12, 5
     C, h, g = W.random_instance(N, M, 71)
     out = []
     for space in (mc.DirectSpace(N, M), mc.build_tables(N, M, form="reduced")):
-        Ct = dev(C).requires_grad_(True)
-        E = mc.energy(Ct, dev(h), dev(g), space)
+        Ct, ht, gt = (dev(x).requires_grad_(True) for x in (C, h, g))
+        E = mc.energy(Ct, ht, gt, space)
         E.real.backward()
-        out.append((E.detach(), Ct.grad))
+        out.append((E.detach(), Ct.grad, ht.grad, gt.grad))
     assert torch.equal(out[0][0], out[1][0])
     assert torch.equal(out[0][1], out[1][1])
-    hg = dev(h).requires_grad_(True)
-    E = mc.energy(dev(C), hg, dev(g), mc.DirectSpace(N, M))
+    for i in (2, 3):
+        assert rel_inf(out[0][i].cpu().numpy(), out[1][i].cpu().numpy()) <= TOL
+    Ct = dev(C).requires_grad_(True)
+    E = mc.energy(Ct, dev(h), dev(g), mc.DirectSpace(N, M), hermitian=False)
     with pytest.raises(ValueError):
         E.real.backward()
+
+
+def test_direct_density_matrices_reject_bad_sizes(mc):
+    C = torch.zeros(mc.dim(1, 9), dtype=torch.complex128, device="cuda")
+    with pytest.raises(mc.MCError):
+        mc.rho1(C, mc.DirectSpace(1, 9))
