@@ -190,9 +190,26 @@ def autograd_leg(dev) -> dict:
     rho1 = _median_ms(lambda: mc.rho1(Cd, tab), 5, stream)
     del tab
     torch.cuda.empty_cache()
+    # the same with no table
+    sp = mc.DirectSpace(N, M, dev)
+    mc.apply_H(hd, gd, Cd, sp, out=HC)
+    plain_d = _median_ms(lambda: mc.apply_H(hd, gd, Cd, sp, out=HC), 10, stream)
+
+    def fwd_bwd_d():
+        for x in (Cg, hg, gg):
+            x.grad = None
+        mc.energy(Cg, hg, gg, sp).real.backward()
+
+    fwd_bwd_d()
+    full_d = _median_ms(fwd_bwd_d, 5, stream)
+    rho2_d = _median_ms(lambda: mc.rho2(Cd, sp), 5, stream)
+    rho1_d = _median_ms(lambda: mc.rho1(Cd, sp), 5, stream)
     return {"workload": f"N={N}, M={M}, dim {C.size}", "plain_apply_ms": plain,
             "energy_fwd_bwd_ms": full, "ratio_fwd_bwd_over_apply": full / plain,
-            "rho1_ms": rho1, "rho2_ms": rho2}
+            "rho1_ms": rho1, "rho2_ms": rho2,
+            "table_free": {"plain_apply_ms": plain_d, "energy_fwd_bwd_ms": full_d,
+                           "ratio_fwd_bwd_over_apply": full_d / plain_d,
+                           "rho1_ms": rho1_d, "rho2_ms": rho2_d}}
 
 
 def sil_leg(dev, N: int = 200, M: int = 5, dt: float = 1e-5, tol: float = 1e-10) -> dict:
