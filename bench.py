@@ -336,7 +336,8 @@ def batched_leg(dev, steps: int = 50, table_free: bool = False) -> dict:
     total_dim = sum(t.dim for t, _, _ in insts)
     print(f"[bench] batched: {len(insts)} instances, total dim {total_dim}; autotuning",
           file=sys.stderr, flush=True)
-    tuned = autotune.tune(insts, cache_path=os.path.join(ROOT, "gpurun_out", "autotune_cache.json"),
+    import tempfile
+    tuned = autotune.tune(insts, cache_path=os.path.join(tempfile.gettempdir(), "mc_autotune_cache.json"),
                           reps=2)
     print(f"[bench] batched: schedule {tuned['schedule']}", file=sys.stderr, flush=True)
     b = Batch(insts, tuned["schedule"])
