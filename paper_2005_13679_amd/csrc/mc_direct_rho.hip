@@ -9,8 +9,10 @@
 // with A, B the amplitudes of mc_apply_H.  The closed-form target covers the
 // coincident-index slots too: a creation into a removed orbital cancels in
 // the prefix sums, so {q,l} = {k,s} gives the row itself and one shared
-// orbital a single jump, with no case analysis.  rho2 is accumulated for the
-// unordered removal pairs (k <= s) and expanded with rho2_ksql = rho2_skql.
+// orbital a single jump, with no case analysis.  rho2 is accumulated for
+// unordered removal pairs (k <= s) and unordered creation pairs (q <= l) and
+// expanded with rho2_ksql = rho2_skql = rho2_kslq (a+_k a+_s and a_q a_l
+// commute; target and amplitudes are symmetric in each pair).
 //
 // Wave w accumulates tiles w, w + W, ... per slot in registers (chunks of
 // kDRhoChunk slots per pass over the tiles), sums each slot over its 64 rows
@@ -116,11 +118,11 @@ __global__ __launch_bounds__(256) void k_drho1(int N, int nbits, int64_t D, int6
                         ldc, sq, part);
 }
 
-// rho2: removal pair P = (K, S), creation slot J = q*M + l.
-template <int MT, int P, int J>
+// rho2: removal pair P = (K, S), creation pair Q = (q, l), both unordered.
+template <int MT, int P, int Q>
 __device__ __forceinline__ int32_t drho2_target(const DirectRow<MT> &row, bool valid)
 {
-    constexpr int K = pair_k(MT, P), S = pair_s(MT, P), q = J / MT, l = J % MT;
+    constexpr int K = pair_k(MT, P), S = pair_s(MT, P), q = pair_k(MT, Q), l = pair_s(MT, Q);
     return valid ? (int32_t)row.template target<K, S, q, l>() : -1;
 }
 
@@ -139,7 +141,7 @@ __device__ __forceinline__ void drho2_tile(std::integer_sequence<int, Is...>,
     ((c[Is] = ldc(t[Is])), ...);
     (
         [&] {
-            constexpr int q = (J0 + Is) / MT, l = (J0 + Is) % MT;
+            constexpr int q = pair_k(MT, J0 + Is), l = pair_s(MT, J0 + Is);
             // creation amplitudes on m = n - e_K - e_S (rows with A = 0 may go below 0)
             const int mq = max(n[q] - (q == K) - (q == S), 0);
             const int ml = max(n[l] - (l == K) - (l == S), 0);
@@ -156,9 +158,9 @@ __device__ __forceinline__ void drho2_chunk(int N, int nbits, int64_t D, int64_t
                                             int nwaves, int wave, const Gather<false> &ldc,
                                             const double *sq, double2 *__restrict__ part)
 {
-    constexpr int NS = MT * MT, NP = MT * (MT + 1) / 2, E = NP * NS;
+    constexpr int NP = MT * (MT + 1) / 2, E = NP * NP;
     constexpr int K = pair_k(MT, P), S = pair_s(MT, P);
-    constexpr int CH = NS - J0 < kDRhoChunk ? NS - J0 : kDRhoChunk;
+    constexpr int CH = NP - J0 < kDRhoChunk ? NP - J0 : kDRhoChunk;
     const int lane = threadIdx.x & 63;
     double ar[CH], ai[CH];
 #pragma unroll
@@ -179,7 +181,7 @@ __device__ __forceinline__ void drho2_chunk(int N, int nbits, int64_t D, int64_t
 #pragma unroll
     for (int i = 0; i < CH; ++i) {
         const double vr = wave_sum(ar[i]), vi = wave_sum(ai[i]);
-        if (lane == 0) part[(int64_t)wave * E + P * NS + J0 + i] = make_double2(vr, vi);
+        if (lane == 0) part[(int64_t)wave * E + P * NP + J0 + i] = make_double2(vr, vi);
     }
 }
 
@@ -198,7 +200,7 @@ __device__ __forceinline__ void drho2_all(std::integer_sequence<int, Ps...>, int
                                           const Gather<false> &ldc, const double *sq,
                                           double2 *__restrict__ part)
 {
-    constexpr int NCH = (MT * MT + kDRhoChunk - 1) / kDRhoChunk;
+    constexpr int NCH = (MT * (MT + 1) / 2 + kDRhoChunk - 1) / kDRhoChunk;
     (drho2_pair<MT, Ps>(std::make_integer_sequence<int, NCH>{}, N, nbits, D, tiles, nwaves, wave,
                         ldc, sq, part),
      ...);
@@ -233,7 +235,7 @@ __global__ void k_drho1_finalize(int E, int nwaves, const double2 *__restrict__ 
     out[e] = make_double2(sr, si);
 }
 
-// rho2[k][s][q][l] from the partials of the unordered pair {k, s}
+// rho2[k][s][q][l] from the partials of the unordered pairs {k, s}, {q, l}
 __global__ void k_drho2_finalize(int M, int nwaves, const double2 *__restrict__ part,
                                  double2 *__restrict__ out)
 {
@@ -241,10 +243,13 @@ __global__ void k_drho2_finalize(int M, int nwaves, const double2 *__restrict__ 
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total) return;
     const int l = idx % M, q = (idx / M) % M, s = (idx / (M * M)) % M, k = idx / (M * M * M);
-    const int a = k < s ? k : s, b = k < s ? s : k;
-    const int p = a * M - a * (a - 1) / 2 + (b - a);
-    const int E = M * (M + 1) / 2 * M * M;
-    const int e = p * M * M + q * M + l;
+    auto pair_of = [M](int x, int y) {
+        const int a = x < y ? x : y, b = x < y ? y : x;
+        return a * M - a * (a - 1) / 2 + (b - a);
+    };
+    const int NP = M * (M + 1) / 2;
+    const int E = NP * NP;
+    const int e = pair_of(k, s) * NP + pair_of(q, l);
     double sr = 0.0, si = 0.0;
     for (int w = 0; w < nwaves; ++w) {
         const double2 v = part[(int64_t)w * E + e];
@@ -271,7 +276,7 @@ int drho_setup(int32_t N, int32_t M, const double *C_d, const double *out_d, con
     size_t need = 0;
     mc_workspace_size(N, M, op, &need);
     if (ws_bytes < need) return MC_ENOMEM;
-    const int64_t E = op == MC_OP_RHO1 ? (int64_t)M * M : (int64_t)npairs(M) * M * M;
+    const int64_t E = op == MC_OP_RHO1 ? (int64_t)M * M : (int64_t)npairs(M) * npairs(M);
     const int64_t tiles = (D + kTile - 1) / kTile;
     int64_t nw = tiles < kDRhoMaxWaves ? tiles : kDRhoMaxWaves;
     const int64_t fit = (int64_t)(ws_bytes / (size_t)(E * 16));
