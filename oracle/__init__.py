@@ -6,11 +6,12 @@ this package.  The GPU library never uses it and shares no code with it.
 
 The oracle is plain and slow on purpose, and follows the paper's definitions:
 
-* ``combinatorics`` -- Eq. (nc) for the dimension, Algorithm 1
-  (configuration -> index) and Algorithm 2 (index -> configuration), written
-  out in pure Python, plus an enumeration of all configurations that does not
-  use the hash.
-* ``native`` -- the same algorithms in plain C (``mc_oracle.c``), plus the
+* ``combinatorics`` -- Eq. (nc) for the dimension, the index of a
+  configuration as the particle cost sum of Eq. (TotalCost) (the map of
+  Algorithm 1) and its inverse by bisection (the map of Algorithm 2), in pure
+  Python, plus an enumeration of all configurations that does not use the
+  hash.
+* ``native`` -- the same maps in plain C (``mc_oracle.c``), plus the
   single/double jump maps by definition and H.C, rho1, rho2 by applying
   creation/annihilation operators to occupation vectors.
 * ``dense`` -- textbook brute force: Kronecker-product ladder operators over

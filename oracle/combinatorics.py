@@ -2,8 +2,9 @@
 
 Follows Sec. III of arXiv:2005.13679:
   * Eq. (nc):  N_c(N, M) = (N + M - 1)! / (N! (M - 1)!),  N_c(n, 0) = 0;
-  * Algorithm 1: occupation vector -> index (sum of particle costs);
-  * Algorithm 2: index -> occupation vector (greedy descent).
+  * Eq. (TotalCost): occupation vector -> index (sum of particle costs),
+    the map of Algorithm 1;
+  * its inverse (the map of Algorithm 2) by bisection on that index.
 Indices and orbitals are 0-based as in the algorithms.
 """
 
@@ -24,42 +25,36 @@ def dim(N: int, M: int) -> int:
     return nc(N, M)
 
 
-def hash_alg1(occ, N: int | None = None) -> int:
-    """Algorithm 1.  Scan orbitals m = M-1 .. 1; for each particle found in
-    orbital m add the cost N_c(s, m), s being the particles still in the
-    basket, then remove the particle from the basket."""
-    M = len(occ)
-    if N is None:
-        N = sum(occ)
-    k = 0
-    s = N
-    for m in range(M - 1, 0, -1):
-        j = occ[m]
-        while j > 0:
-            k += nc(s, m)
-            s -= 1
-            j -= 1
-    return k
+def index_of(occ) -> int:
+    """Configuration -> index from Eq. (TotalCost): the particles, listed by
+    nondecreasing orbital, cost N_c(i, p_i) each (i = 1..N); the index is the
+    total.  (The map of Algorithm 1, evaluated from the lowest orbital up.)"""
+    positions = [m for m in range(len(occ)) for _ in range(occ[m])]
+    return total_cost(positions, len(occ))
 
 
-def unhash_alg2(beta: int, N: int, M: int) -> list[int]:
-    """Algorithm 2.  Starting from orbital M-1, move a particle from the
-    basket into orbital m while the remaining index covers its cost N_c(s, m);
-    otherwise go down one orbital.  Leftover particles go to orbital 0."""
+def config_of(beta: int, N: int, M: int) -> list[int]:
+    """Index -> configuration by bisection on ``index_of``.  Orbital M-1 is
+    the most significant; with the orbitals above m fixed, the first
+    configuration with n_m = t keeps the rest in orbital 0 and its index
+    grows with t, so n_m is the largest t whose first configuration does not
+    exceed beta.  The remainder goes to orbital 0."""
     if not (0 <= beta < nc(N, M)):
         raise ValueError("index out of range")
     n = [0] * M
-    k = beta
-    m = M - 1
-    s = N
-    while k > 0:
-        while k - nc(s, m) < 0:
-            m -= 1
-        k -= nc(s, m)
-        n[m] += 1
-        s -= 1
-    if s > 0:
-        n[0] += s
+    left = N
+    for m in range(M - 1, 0, -1):
+        lo, hi = 0, left
+        while lo < hi:
+            mid = (lo + hi + 1) // 2
+            n[m], n[0] = mid, left - mid
+            if index_of(n) <= beta:
+                lo = mid
+            else:
+                hi = mid - 1
+        n[m], n[0] = lo, 0
+        left -= lo
+    n[0] = left
     return n
 
 

@@ -19,7 +19,7 @@ import itertools
 import numpy as np
 import scipy.sparse as sp
 
-from .combinatorics import hash_alg1, nc
+from .combinatorics import index_of, nc
 
 
 def _ladder_ops(N: int, M: int):
@@ -50,7 +50,7 @@ def _restriction(N: int, M: int):
         flat = 0
         for o in occ:
             flat = flat * d + o
-        rows.append(hash_alg1(list(occ), N))
+        rows.append(index_of(list(occ)))
         cols.append(flat)
     P = sp.csr_matrix((np.ones(len(rows)), (rows, cols)), shape=(D, d ** M))
     return P

@@ -10,8 +10,9 @@
  *
  * Deliberately plain and slow:
  *   - N_c(n, m) is recomputed from its binomial definition on every use;
- *   - configuration -> index is Algorithm 1 executed particle by particle;
- *   - index -> configuration is Algorithm 2 executed particle by particle;
+ *   - configuration -> index is the total particle cost of Eq. (TotalCost),
+ *     one particle at a time;
+ *   - index -> configuration bisects on that rank, orbital by orbital;
  *   - H.C and the density matrices are obtained by applying creation and
  *     annihilation operators to occupation vectors, one operator at a time,
  *     with no jump tables and no case table;
@@ -47,41 +48,52 @@ int64_t orc_nc(int64_t n, int64_t m)
     return (int64_t)r;
 }
 
-/* Algorithm 1: occupation vector -> index.  Orbitals are scanned from M-1
- * down to 1; each particle found adds the cost N_c(s, m) of the particles
- * still in the basket, and the basket loses one particle. */
+/* Configuration -> index, written from Eq. (TotalCost): list the particles
+ * by nondecreasing orbital, p_1 <= p_2 <= ... <= p_N; particle i (1-based)
+ * costs N_c(i, p_i), and the index is the total cost.  Particles in orbital
+ * 0 cost nothing (N_c(i, 0) = 0).  This is the same map Algorithm 1
+ * computes, evaluated from the lowest orbital up and without a basket. */
 int64_t orc_hash(int32_t N, int32_t M, const int32_t *n)
 {
-    int64_t k = 0;
-    int64_t s = N;
-    for (int32_t m = M - 1; m >= 1; --m) {
-        int32_t j = n[m];
-        while (j > 0) {
-            k += orc_nc(s, m);
-            s -= 1;
-            j -= 1;
+    (void)N;
+    int64_t index = 0;
+    int64_t i = 0;                          /* particles listed so far */
+    for (int32_t orb = 0; orb < M; ++orb) {
+        for (int32_t c = 0; c < n[orb]; ++c) {
+            ++i;
+            index += orc_nc(i, orb);
         }
     }
-    return k;
+    return index;
 }
 
-/* Algorithm 2: index -> occupation vector, by greedy descent from orbital
- * M-1; particles left in the basket go to orbital 0.  Returns 0 on success,
- * -1 if beta is outside [0, N_c(N, M)). */
+/* Index -> configuration, by bisection on the rank of orc_hash.  The order
+ * compares n_{M-1} first, then n_{M-2}, ... (orbital M-1 most significant).
+ * With the orbitals above m already fixed and `left` particles still to
+ * place, the first configuration with n_m = t puts the other left - t
+ * particles into orbital 0, and its rank grows with t; so n_m is the largest
+ * t whose first configuration does not rank above beta.  What is left after
+ * orbital 1 goes to orbital 0.  Returns 0 on success, -1 if beta is outside
+ * [0, N_c(N, M)). */
 int orc_unhash(int32_t N, int32_t M, int64_t beta, int32_t *n)
 {
     if (beta < 0 || beta >= orc_nc(N, M)) return -1;
     for (int32_t i = 0; i < M; ++i) n[i] = 0;
-    int64_t k = beta;
-    int32_t m = M - 1;
-    int64_t s = N;
-    while (k > 0) {
-        while (k - orc_nc(s, m) < 0) m -= 1;
-        k -= orc_nc(s, m);
-        n[m] += 1;
-        s -= 1;
+    int32_t left = N;
+    for (int32_t m = M - 1; m >= 1; --m) {
+        int32_t lo = 0, hi = left;          /* invariant: rank(lo) <= beta */
+        while (lo < hi) {
+            int32_t mid = lo + (hi - lo + 1) / 2;
+            n[m] = mid;
+            n[0] = left - mid;
+            if (orc_hash(N, M, n) <= beta) lo = mid;
+            else hi = mid - 1;
+        }
+        n[m] = lo;
+        n[0] = 0;
+        left -= lo;
     }
-    if (s > 0) n[0] += (int32_t)s;
+    n[0] = left;
     return 0;
 }
 
@@ -367,7 +379,7 @@ void orc_t2_rows(int32_t N, int32_t M, const int64_t *rows, int64_t nrows,
  * conversion is needed there).  This map keeps the rest: for each valid
  * removal pair (k, s), k <= s, in lexicographic order, the creation pairs
  * (q, l), q <= l, with q and l both outside {k, s}, in lexicographic order;
- * each entry is the index of n - e_k - e_s + e_q + e_l (Algorithm 1). */
+ * each entry is the index of n - e_k - e_s + e_q + e_l (Eq. TotalCost). */
 static int64_t reduced_pair_slots(int32_t M, const int32_t *n)
 {
     int64_t c = 0;
@@ -419,7 +431,7 @@ void orc_t2r_rows(int32_t N, int32_t M, const int64_t *rows, int64_t nrows,
     }
 }
 
-/* Hash a list of occupation vectors with Algorithm 1. */
+/* Index of each occupation vector in a list (Eq. TotalCost). */
 void orc_hash_rows(int32_t N, int32_t M, const int32_t *occ, int64_t nrows,
                    int64_t *idx)
 {

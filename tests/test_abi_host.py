@@ -89,7 +89,7 @@ def test_hash_unhash_full_enumeration(N, M):
     import paper_2005_13679_amd as mc
     for c in cb.compositions(N, M):
         i = mc.hash_occ(N, M, c)
-        assert i == cb.hash_alg1(c)
+        assert i == cb.index_of(c)
         assert list(mc.unhash(N, M, i)) == c
 
 

@@ -1,4 +1,5 @@
-"""Pins for the oracle's dimension, Algorithm 1 and Algorithm 2 (CPU only)."""
+"""Pins for the oracle's dimension and its configuration <-> index maps
+(the maps of Algorithms 1 and 2; CPU only)."""
 
 import math
 
@@ -20,14 +21,27 @@ def hockey_stick_index(occ):
                for m in range(1, len(occ)))
 
 
+def order_rank(occ):
+    """Position of a configuration in the order the algorithms define
+    (orbital M-1 most significant): the number of configurations that come
+    before it, counted block by block -- for each orbital m from M-1 down,
+    the configurations that agree above m and hold fewer particles in m."""
+    left = sum(occ)
+    rank = 0
+    for m in range(len(occ) - 1, 0, -1):
+        rank += sum(cb.nc(left - t, m) for t in range(occ[m]))
+        left -= occ[m]
+    return rank
+
+
 def test_worked_example_fig_scheme2(oracle_native):
     ex = golden("hash_worked_example.json")
     N, M, occ = ex["N"], ex["M"], ex["occupation"]
     terms = [cb.nc(n, m) for n, m in ex["cost_terms"]]
     assert sum(terms) == ex["index"]
-    assert cb.hash_alg1(occ) == ex["index"]
+    assert cb.index_of(occ) == ex["index"]
     assert oracle_native.hash_occ(occ, N) == ex["index"]
-    assert cb.unhash_alg2(ex["index"], N, M) == occ
+    assert cb.config_of(ex["index"], N, M) == occ
     assert list(oracle_native.unhash(ex["index"], N, M)) == occ
     # Eq. (TotalCost) with sorted particle positions: orbital 1 once, orbital 3 twice
     assert cb.total_cost([1, 3, 3], M) == ex["index"]
@@ -53,8 +67,8 @@ def test_dimension_edge_cases(oracle_native):
 def test_hand_derived_order_two_particles_three_orbitals():
     # orbital M-1 most significant: sorted by (n2, n1) with n0 the remainder
     expected = [[2, 0, 0], [1, 1, 0], [0, 2, 0], [1, 0, 1], [0, 1, 1], [0, 0, 2]]
-    assert [cb.unhash_alg2(i, 2, 3) for i in range(6)] == expected
-    assert [cb.hash_alg1(o) for o in expected] == list(range(6))
+    assert [cb.config_of(i, 2, 3) for i in range(6)] == expected
+    assert [cb.index_of(o) for o in expected] == list(range(6))
 
 
 def test_single_particle_maps_to_its_orbital(oracle_native):
@@ -62,7 +76,7 @@ def test_single_particle_maps_to_its_orbital(oracle_native):
         for j in range(M):
             e = [0] * M
             e[j] = 1
-            assert cb.hash_alg1(e) == j
+            assert cb.index_of(e) == j
             assert oracle_native.hash_occ(e, 1) == j
 
 
@@ -73,22 +87,25 @@ def test_bijection_full_enumeration(oracle_native, N, M):
     D = cb.dim(N, M)
     configs = list(cb.compositions(N, M))
     assert len(configs) == D
-    idx = [cb.hash_alg1(c) for c in configs]
+    idx = [cb.index_of(c) for c in configs]
     assert sorted(idx) == list(range(D))
+    # brute force: the index is the position in the order that compares
+    # n_{M-1} first, then n_{M-2}, ..., n_1
+    ordered = sorted(configs, key=lambda c: tuple(reversed(c[1:])))
+    assert [cb.index_of(c) for c in ordered] == list(range(D))
     for c, i in zip(configs, idx):
-        assert cb.unhash_alg2(i, N, M) == c
+        assert cb.config_of(i, N, M) == c
     occ = np.array(configs, dtype=np.int32)
     assert np.array_equal(oracle_native.hash_rows(occ, N), np.array(idx))
     assert np.array_equal(oracle_native.occ_rows(N, M, np.array(idx)), occ)
 
 
 @pytest.mark.parametrize("N,M", [(3, 5), (7, 4), (6, 6), (12, 3)])
-def test_alg1_equals_total_cost_and_closed_form(N, M):
+def test_index_equals_closed_form_and_block_count(N, M):
     for c in cb.compositions(N, M):
-        pos = [m for m in range(M) for _ in range(c[m])]
-        i = cb.hash_alg1(c)
-        assert cb.total_cost(pos, M) == i
+        i = cb.index_of(c)
         assert hockey_stick_index(c) == i
+        assert order_rank(c) == i
 
 
 def test_extreme_indices(oracle_native):
@@ -120,7 +137,7 @@ def test_roundtrip_property(N, M, data):
     cuts = sorted(data.draw(st.lists(st.integers(0, N), min_size=M - 1, max_size=M - 1)))
     bounds = [0] + cuts + [N]
     occ = [bounds[i + 1] - bounds[i] for i in range(M)]
-    i = cb.hash_alg1(occ)
+    i = cb.index_of(occ)
     assert 0 <= i < cb.dim(N, M)
-    assert cb.unhash_alg2(i, N, M) == occ
+    assert cb.config_of(i, N, M) == occ
     assert hockey_stick_index(occ) == i

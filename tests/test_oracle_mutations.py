@@ -26,8 +26,10 @@ MUTATIONS = {
                     "double hr = h[2 * (l * M + k)], hi = h[2 * (l * M + k) + 1];"),
     "creation_amplitude_off_by_one": ("    n[j] += 1;\n    return (double)n[j];",
                                       "    n[j] += 1;\n    return (double)(n[j] > 1 ? n[j] - 1 : 1);"),
-    "alg1_basket_before_cost": ("            k += orc_nc(s, m);\n            s -= 1;",
-                                "            s -= 1;\n            k += orc_nc(s, m);"),
+    "total_cost_particle_count_off_by_one": ("            ++i;\n            index += orc_nc(i, orb);",
+                                             "            index += orc_nc(i, orb);\n            ++i;"),
+    "unhash_bisection_keeps_lower_bound": ("            if (orc_hash(N, M, n) <= beta) lo = mid;",
+                                           "            if (orc_hash(N, M, n) < beta) lo = mid;"),
     "rho_missing_conjugate": ("double ar = C[2 * gamma], ai = -C[2 * gamma + 1];\n        double br = C[2 * beta], bi = C[2 * beta + 1];\n        nadd(&re, amp * (ar * br - ai * bi));\n        nadd(&im, amp * (ar * bi + ai * br));\n    }\n    out[0] = nval(&re);\n    out[1] = nval(&im);\n}\n\nvoid orc_rho1",
                               "double ar = C[2 * gamma], ai = C[2 * gamma + 1];\n        double br = C[2 * beta], bi = C[2 * beta + 1];\n        nadd(&re, amp * (ar * br - ai * bi));\n        nadd(&im, amp * (ar * bi + ai * br));\n    }\n    out[0] = nval(&re);\n    out[1] = nval(&im);\n}\n\nvoid orc_rho1"),
     # counts only (the row writer keeps the right rule, so rows get shorter
@@ -40,7 +42,7 @@ MUTATIONS = {
     "reduced_map_keeps_shared_orbital": (
         "                        if (q == k || q == s || l == k || l == s) continue;",
         "                        if (q == k || l == s) continue;"),
-    "unhash_remainder_dropped": ("    if (s > 0) n[0] += (int32_t)s;\n    return 0;",
+    "unhash_remainder_dropped": ("    n[0] = left;\n    return 0;",
                                  "    return 0;"),
 }
 
@@ -140,7 +142,7 @@ def pin_checks(native):
                             m[s] -= 1
                             m[q] += 1
                             m[l] += 1
-                            want.append(cb.hash_alg1(list(m)))
+                            want.append(cb.index_of(list(m)))
             assert list(ent[off[gam]:off[gam + 1]]) == want
 
     for name, fn in [("worked_example", worked_example), ("reduced_map", reduced_map), ("bijection", bijection),

@@ -56,7 +56,7 @@ def test_fig_jump_illustration_counts(oracle_native):
         n[s] -= 1
         n[0] += 1
         n[0] += 1
-        assert ent[start] == cb.hash_alg1(list(n))
+        assert ent[start] == cb.index_of(list(n))
 
 
 @pytest.mark.parametrize("N,M", [(2, 3), (5, 4), (10, 5), (7, 6)])
@@ -76,7 +76,7 @@ def test_double_jump_definition(oracle_native, N, M):
                     m[s] -= 1
                     m[q] += 1
                     m[l] += 1
-                    assert row[p * M * M + q * M + l] == cb.hash_alg1(list(m))
+                    assert row[p * M * M + q * M + l] == cb.index_of(list(m))
 
 
 @pytest.mark.parametrize("N,M", [(2, 2), (5, 3), (10, 5), (20, 4), (8, 7)])
@@ -121,7 +121,7 @@ def test_reduced_double_jump_definition(oracle_native, N, M):
                 m[s] -= 1
                 m[q] += 1
                 m[l] += 1
-                want.append(cb.hash_alg1(list(m)))
+                want.append(cb.index_of(list(m)))
         assert list(row) == want
 
 
