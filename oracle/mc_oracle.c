@@ -9,7 +9,8 @@
  * CPU-baseline leg use it.  It shares no code with the GPU library.
  *
  * Deliberately plain and slow:
- *   - N_c(n, m) is recomputed from its binomial definition on every use;
+ *   - N_c(n, m) comes from its binomial definition (small arguments from a
+ *     table of the same values, filled once at load);
  *   - configuration -> index is the total particle cost of Eq. (TotalCost),
  *     one particle at a time;
  *   - index -> configuration bisects on that rank, orbital by orbital;
@@ -27,6 +28,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <omp.h>
 
 #define ORC_MAXM 64
 
@@ -34,7 +36,7 @@
 /* Eq. (nc): N_c(n, m) = (n + m - 1)! / (n! (m - 1)!), with N_c(n, 0) = 0   */
 /* (Eq. TotalCost).  Returns -1 if the value does not fit in int64.         */
 /* ---------------------------------------------------------------------- */
-int64_t orc_nc(int64_t n, int64_t m)
+static int64_t nc_definition(int64_t n, int64_t m)
 {
     if (m <= 0 || n < 0) return 0;
     int64_t a = n + m - 1;          /* C(a, b) with b = m - 1 */
@@ -46,6 +48,26 @@ int64_t orc_nc(int64_t n, int64_t m)
         if (r > (unsigned __int128)INT64_MAX) return -1;
     }
     return (int64_t)r;
+}
+
+/* The hash below asks for N_c(i, m) once per particle, so small arguments
+ * are answered from a table that nc_definition fills once when the library
+ * is loaded; everything else is computed from the definition. */
+#define ORC_NC_TAB_N 4096
+#define ORC_NC_TAB_M 32
+static int64_t nc_table[ORC_NC_TAB_M][ORC_NC_TAB_N];
+
+__attribute__((constructor)) static void nc_table_fill(void)
+{
+    for (int64_t m = 0; m < ORC_NC_TAB_M; ++m)
+        for (int64_t n = 0; n < ORC_NC_TAB_N; ++n)
+            nc_table[m][n] = nc_definition(n, m);
+}
+
+int64_t orc_nc(int64_t n, int64_t m)
+{
+    if (n >= 0 && n < ORC_NC_TAB_N && m >= 0 && m < ORC_NC_TAB_M) return nc_table[m][n];
+    return nc_definition(n, m);
 }
 
 /* Configuration -> index, written from Eq. (TotalCost): list the particles
@@ -193,94 +215,110 @@ void orc_apply_h_rows(int32_t N, int32_t M, const double *h, const double *g,
     }
 }
 
-/* One element of the one-body density matrix, Eq. (rho1):
- *   rho_kl = sum_gamma conj(C_gamma) <gamma|a+_k a_l|beta> C_beta. */
-static void rho1_element(int32_t N, int32_t M, int64_t D, const double *C,
-                         int32_t k, int32_t l, double *out)
+/* Density matrices, Eqs. (rho1) and (rho2):
+ *   rho_kl   = sum_gamma conj(C_gamma) <gamma|a+_k a_l|beta> C_beta,
+ *   rho_ksql = sum_gamma conj(C_gamma) <gamma|a+_k a+_s a_q a_l|beta> C_beta,
+ * with <gamma|O|beta> found, as in H.C, by applying O^dagger to |gamma>.
+ * Each configuration gamma is decoded once and visited for every requested
+ * element; each thread sums its share of the rows with Neumaier
+ * compensation, and the per-thread sums are then added in thread order. */
+typedef struct { nsum re, im; } csum;
+
+/* amplitude product of O^dagger applied to n (modified in place), 0 if it
+ * annihilates the state; body = 1: a+_l a_k; body = 2: a+_l a+_q a_s a_k */
+static double adjoint_string(int32_t *n, int body, int32_t k, int32_t s,
+                             int32_t q, int32_t l)
 {
-    nsum re = {0, 0}, im = {0, 0};
-    int32_t n[ORC_MAXM];
-    for (int64_t gamma = 0; gamma < D; ++gamma) {
-        orc_unhash(N, M, gamma, n);
-        double amp2 = annihilate(n, k);
-        if (amp2 == 0.0) continue;
-        amp2 *= create(n, l);
-        double amp = sqrt(amp2);
-        int64_t beta = orc_hash(N, M, n);
-        double ar = C[2 * gamma], ai = -C[2 * gamma + 1];
-        double br = C[2 * beta], bi = C[2 * beta + 1];
-        nadd(&re, amp * (ar * br - ai * bi));
-        nadd(&im, amp * (ar * bi + ai * br));
+    double amp2 = annihilate(n, k);
+    if (amp2 == 0.0) return 0.0;
+    if (body == 2) {
+        double f = annihilate(n, s);
+        if (f == 0.0) return 0.0;
+        amp2 *= f;
+        amp2 *= create(n, q);
     }
-    out[0] = nval(&re);
-    out[1] = nval(&im);
+    amp2 *= create(n, l);
+    return amp2;
+}
+
+/* elems[e] = flat element index (k*M + l, or ((k*M + s)*M + q)*M + l) */
+static void density_elements(int32_t N, int32_t M, const double *C, int body,
+                             const int64_t *elems, int64_t count, double *out)
+{
+    int64_t D = orc_nc(N, M);
+    int nthreads = 1;
+#pragma omp parallel
+    {
+#pragma omp single
+        nthreads = omp_get_num_threads();
+    }
+    csum *part = calloc((size_t)nthreads * (size_t)count, sizeof(csum));
+    if (!part) return;
+#pragma omp parallel num_threads(nthreads)
+    {
+        csum *mine = part + (size_t)omp_get_thread_num() * (size_t)count;
+        int32_t n0[ORC_MAXM], n[ORC_MAXM];
+#pragma omp for schedule(static)
+        for (int64_t gamma = 0; gamma < D; ++gamma) {
+            orc_unhash(N, M, gamma, n0);
+            double ar = C[2 * gamma], ai = -C[2 * gamma + 1];   /* conj(C_gamma) */
+            for (int64_t e = 0; e < count; ++e) {
+                int64_t t = elems[e];
+                int32_t k, s = 0, q = 0, l;
+                l = (int32_t)(t % M); t /= M;
+                if (body == 2) {
+                    q = (int32_t)(t % M); t /= M;
+                    s = (int32_t)(t % M); t /= M;
+                }
+                k = (int32_t)t;
+                memcpy(n, n0, sizeof(int32_t) * M);
+                double amp2 = adjoint_string(n, body, k, s, q, l);
+                if (amp2 == 0.0) continue;
+                double amp = sqrt(amp2);
+                int64_t beta = orc_hash(N, M, n);
+                double br = C[2 * beta], bi = C[2 * beta + 1];
+                nadd(&mine[e].re, amp * (ar * br - ai * bi));
+                nadd(&mine[e].im, amp * (ar * bi + ai * br));
+            }
+        }
+    }
+    for (int64_t e = 0; e < count; ++e) {
+        nsum re = {0, 0}, im = {0, 0};
+        for (int th = 0; th < nthreads; ++th) {
+            nadd(&re, nval(&part[(size_t)th * (size_t)count + (size_t)e].re));
+            nadd(&im, nval(&part[(size_t)th * (size_t)count + (size_t)e].im));
+        }
+        out[2 * e] = nval(&re);
+        out[2 * e + 1] = nval(&im);
+    }
+    free(part);
+}
+
+static void density_all(int32_t N, int32_t M, const double *C, int body, double *out)
+{
+    int64_t count = body == 1 ? (int64_t)M * M : (int64_t)M * M * M * M;
+    int64_t *elems = malloc((size_t)count * sizeof(int64_t));
+    if (!elems) return;
+    for (int64_t e = 0; e < count; ++e) elems[e] = e;
+    density_elements(N, M, C, body, elems, count, out);
+    free(elems);
 }
 
 void orc_rho1(int32_t N, int32_t M, const double *C, double *rho1)
 {
-    int64_t D = orc_nc(N, M);
-#pragma omp parallel for schedule(dynamic, 1)
-    for (int32_t e = 0; e < M * M; ++e)
-        rho1_element(N, M, D, C, e / M, e % M, rho1 + 2 * e);
-}
-
-/* One element of the two-body density matrix, Eq. (rho2):
- *   rho_ksql = sum_gamma conj(C_gamma) <gamma|a+_k a+_s a_q a_l|beta> C_beta. */
-static void rho2_element(int32_t N, int32_t M, int64_t D, const double *C,
-                         int32_t k, int32_t s, int32_t q, int32_t l,
-                         double *out)
-{
-    nsum re = {0, 0}, im = {0, 0};
-    int32_t n[ORC_MAXM];
-    for (int64_t gamma = 0; gamma < D; ++gamma) {
-        orc_unhash(N, M, gamma, n);
-        double amp2 = annihilate(n, k);
-        if (amp2 == 0.0) continue;
-        double f = annihilate(n, s);
-        if (f == 0.0) continue;
-        amp2 *= f;
-        amp2 *= create(n, q);
-        amp2 *= create(n, l);
-        double amp = sqrt(amp2);
-        int64_t beta = orc_hash(N, M, n);
-        double ar = C[2 * gamma], ai = -C[2 * gamma + 1];
-        double br = C[2 * beta], bi = C[2 * beta + 1];
-        nadd(&re, amp * (ar * br - ai * bi));
-        nadd(&im, amp * (ar * bi + ai * br));
-    }
-    out[0] = nval(&re);
-    out[1] = nval(&im);
+    density_all(N, M, C, 1, rho1);
 }
 
 /* Selected elements of rho2: idx[e] = ((k*M + s)*M + q)*M + l. */
 void orc_rho2_elements(int32_t N, int32_t M, const double *C,
                        const int64_t *idx, int64_t count, double *out)
 {
-    int64_t D = orc_nc(N, M);
-#pragma omp parallel for schedule(dynamic, 1)
-    for (int64_t e = 0; e < count; ++e) {
-        int64_t t = idx[e];
-        int32_t l = (int32_t)(t % M); t /= M;
-        int32_t q = (int32_t)(t % M); t /= M;
-        int32_t s = (int32_t)(t % M); t /= M;
-        int32_t k = (int32_t)t;
-        rho2_element(N, M, D, C, k, s, q, l, out + 2 * e);
-    }
+    density_elements(N, M, C, 2, idx, count, out);
 }
 
 void orc_rho2(int32_t N, int32_t M, const double *C, double *rho2)
 {
-    int64_t D = orc_nc(N, M);
-    int64_t total = (int64_t)M * M * M * M;
-#pragma omp parallel for schedule(dynamic, 1)
-    for (int64_t e = 0; e < total; ++e) {
-        int64_t t = e;
-        int32_t l = (int32_t)(t % M); t /= M;
-        int32_t q = (int32_t)(t % M); t /= M;
-        int32_t s = (int32_t)(t % M); t /= M;
-        int32_t k = (int32_t)t;
-        rho2_element(N, M, D, C, k, s, q, l, rho2 + 2 * e);
-    }
+    density_all(N, M, C, 2, rho2);
 }
 
 /* Occupation vectors of a list of rows (the "hashing table" rows). */

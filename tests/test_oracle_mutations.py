@@ -30,8 +30,8 @@ MUTATIONS = {
                                              "            index += orc_nc(i, orb);\n            ++i;"),
     "unhash_bisection_keeps_lower_bound": ("            if (orc_hash(N, M, n) <= beta) lo = mid;",
                                            "            if (orc_hash(N, M, n) < beta) lo = mid;"),
-    "rho_missing_conjugate": ("double ar = C[2 * gamma], ai = -C[2 * gamma + 1];\n        double br = C[2 * beta], bi = C[2 * beta + 1];\n        nadd(&re, amp * (ar * br - ai * bi));\n        nadd(&im, amp * (ar * bi + ai * br));\n    }\n    out[0] = nval(&re);\n    out[1] = nval(&im);\n}\n\nvoid orc_rho1",
-                              "double ar = C[2 * gamma], ai = C[2 * gamma + 1];\n        double br = C[2 * beta], bi = C[2 * beta + 1];\n        nadd(&re, amp * (ar * br - ai * bi));\n        nadd(&im, amp * (ar * bi + ai * br));\n    }\n    out[0] = nval(&re);\n    out[1] = nval(&im);\n}\n\nvoid orc_rho1"),
+    "rho_missing_conjugate": ("double ar = C[2 * gamma], ai = -C[2 * gamma + 1];   /* conj(C_gamma) */",
+                              "double ar = C[2 * gamma], ai = C[2 * gamma + 1];"),
     # counts only (the row writer keeps the right rule, so rows get shorter
     # than their lengths, never longer)
     "same_orbital_removal_one_particle": ("            if (k == s) { if (n[k] >= 2) ++p; }",
