@@ -396,6 +396,9 @@ def main(argv=None):
     ap.add_argument("--extras", action="store_true", help="also time rho1/rho2 passes")
     ap.add_argument("--quick", action="store_true",
                     help="skip the other apply paths and the autograd and batched legs")
+    ap.add_argument("--only", default=None,
+                    choices=["autograd", "lieb_liniger", "sil", "batched", "batched_table_free"],
+                    help="run one secondary leg alone and print its JSON (for profiling)")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="run one elementwise copy of this size first (HBM counter scale)")
     args = ap.parse_args(argv)
@@ -407,6 +410,16 @@ def main(argv=None):
     import torch
     import paper_2005_13679_amd as mc
     import workloads as W
+
+    if args.only:
+        dev = torch.device("cuda", 0)
+        torch.cuda.set_device(dev)
+        legs = {"autograd": autograd_leg, "lieb_liniger": lieb_liniger_leg, "sil": sil_leg,
+                "batched": batched_leg,
+                "batched_table_free": lambda d: batched_leg(d, table_free=True)}
+        print(f"[bench] leg {args.only}", file=sys.stderr, flush=True)
+        print(json.dumps({args.only: legs[args.only](dev)}), flush=True)
+        return 0
 
     wl = WORKLOADS[args.workload]
     N, M, seed = wl["N"], wl["M"], wl["seed"]

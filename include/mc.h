@@ -142,6 +142,24 @@ typedef struct mc_table_sizes {
 /* Sizes of every table for (N, M).  Host only.  MC_ERANGE if D >= 2^31. */
 int mc_tables_size(int32_t N, int32_t M, mc_table_sizes *out);
 
+/* Device bytes the tables of (N, M) take in `form`: binomials, occupations,
+ * single-jump map, pair mask and offsets, plus (with_double_jumps != 0) the
+ * tiled double-jump map at its largest, i.e. with a block for every removal
+ * pair in every tile (a built map is at most this; the exact size is
+ * t2_required after mc_build_jump_tables).  Host only; errors as
+ * mc_tables_size, MC_EINVAL for an unknown form. */
+int mc_tables_bytes(int32_t N, int32_t M, int32_t form, int32_t with_double_jumps,
+                    int64_t *bytes);
+
+/* HBM budget for the double-jump maps of many instances (a batch): keep[i]
+ * = 1 for the instances that get a map, 0 for those that chain single jumps
+ * instead.  Maps (sized as in mc_tables_bytes) are admitted smallest first,
+ * ties by position, while their total stays within budget_bytes, so the most
+ * instances are served.  N[count], M[count], keep[count] are host arrays.
+ * Host only; MC_EINVAL / MC_ERANGE for a bad instance. */
+int mc_choose_double_jumps(int32_t count, const int32_t *N, const int32_t *M, int32_t form,
+                           double budget_bytes, int32_t *keep);
+
 typedef struct mc_tables {
     int32_t N, M;
     int64_t dim, tiles;
@@ -270,6 +288,22 @@ int mc_apply_H_direct(int32_t N, int32_t M, const double *h_d, const double *g_d
                       const double *C_d, double *HC_d, void *ws_d, size_t ws_bytes,
                       mc_stream stream);
 
+/* HC_d = H^dagger . C_d with no table (h -> h^dagger, g_ksql -> conj(g_lqsk)),
+ * the table-free counterpart of mc_apply_H_adjoint; arguments, limits and
+ * errors as mc_apply_H_direct. */
+int mc_apply_H_direct_adjoint(int32_t N, int32_t M, const double *h_d, const double *g_d,
+                              const double *C_d, double *HC_d, void *ws_d, size_t ws_bytes,
+                              mc_stream stream);
+
+/* flag_d[0] (int32, device) = 1 if h_kl == conj(h_lk) for all k, l and
+ * g_ksql == conj(g_lqsk) for all k, s, q, l (exact comparisons), else 0.  In
+ * the first case H^dagger = H (Sec. II) and mc_apply_H_adjoint equals
+ * mc_apply_H; the energy gradient uses this to skip the adjoint apply.  The
+ * test is sufficient, not necessary: a g that is Hermitian only after the
+ * k <-> s, q <-> l symmetrisation gives 0.  One small kernel on `stream`. */
+int mc_is_hermitian(int32_t M, const double *h_d, const double *g_d, int32_t *flag_d,
+                    mc_stream stream);
+
 /* rho1_d [M*M] = <a+_k a_l> (Eq. rho1) through the single-jump map.
  * Deterministic fixed-order reduction in ws_d (mc_workspace_size(RHO1)). */
 int mc_rho1(int32_t N, int32_t M, const mc_tables *t, const double *C_d,
@@ -396,6 +430,30 @@ int mc_batch_lanczos_orth(const mc_batch *b, double *w_d, const double *v_d,
 int mc_batch_normalize(const mc_batch *b, const double *w_d, double *out_d, double *beta_d,
                        mc_stream stream);
 
+/* A captured sequence of batch calls, replayed as one HIP graph. */
+typedef struct mc_graph mc_graph;
+
+/* Captures `steps` three-term Lanczos steps (no reorthogonalisation; the
+ * recurrence of Sec. VI) of every instance of batch b into one HIP graph:
+ *   normalize(v0) -> V[0], beta row `steps`;
+ *   step j: apply(V[j%3]) -> w; dot(V[j%3], w) -> alpha row j;
+ *           orth(w, V[j%3], V[(j-1)%3], alpha row j, beta row j-1);
+ *           normalize(w) -> V[(j+1)%3], beta row j.
+ * All device buffers: v0_d (batch vector, read at every launch), V_d (three
+ * batch vectors back to back), w_d (batch vector, no overlap with V_d),
+ * alpha_d complex128 [steps][count], beta_d double [steps+1][count]; each
+ * row in the caller's instance order.  `stream` must be a non-null stream
+ * that is not capturing; the capture (thread-local mode) enqueues nothing,
+ * so nothing runs until mc_graph_launch.  Free with mc_graph_destroy; the
+ * batch and every buffer must outlive the graph.  MC_EINVAL on bad
+ * arguments, MC_EHIP if capture or instantiation fails. */
+int mc_batch_lanczos_graph(const mc_batch *b, int32_t steps, const double *v0_d, double *V_d,
+                           double *w_d, double *alpha_d, double *beta_d, mc_stream stream,
+                           mc_graph **out);
+/* Enqueues one replay of the graph on `stream`. */
+int mc_graph_launch(const mc_graph *g, mc_stream stream);
+int mc_graph_destroy(mc_graph *g);
+
 /* ------------------------------------------------------------------------ */
 /* Lanczos building blocks (Sec. VI: Lanczos tridiagonalisation with full   */
 /* reorthogonalisation).  Scalars stay on the device.                        */
@@ -436,6 +494,18 @@ int mc_zgemv_n(int32_t K, int64_t n, const double *V_d, int64_t ldv, const doubl
  * that Sec. II names for time-dependent problems (C(t+dt) ~ |C| V_K y).
  * 1 <= K <= 512, else MC_EINVAL.  Host only. */
 int mc_tridiag_expv(int32_t K, const double *alpha, const double *beta, double dt, double *y);
+
+/* Coefficients of a Short Iterative Lanczos step (Sec. II) after K Lanczos
+ * steps of (H, C/|C|) with coefficients alpha[K], beta[K-1] and the norm
+ * beta_next left after step K: coef[2K] (interleaved complex, host) =
+ * norm_c * exp(-i T_K dt) e_0, so that C(t+dt) ~ sum_j coef_j v_j
+ * (mc_zgemv_n); *err = norm_c * beta_next * |y_{K-1}|, the weight the next
+ * Krylov vector would receive (the step's error estimate); *invariant = 1
+ * and *err = 0 when beta_next < 1e-14 max(1, |alpha[K-1]|) (the Krylov space
+ * is invariant and the step exact), else 0.  Host only; MC_EINVAL as
+ * mc_tridiag_expv or for a null output. */
+int mc_sil_coefficients(int32_t K, const double *alpha, const double *beta, double beta_next,
+                        double norm_c, double dt, double *coef, double *err, int32_t *invariant);
 
 /* Lowest eigenvalue of the real symmetric tridiagonal matrix with diagonal
  * alpha[K] and off-diagonal beta[K-1] (host arrays), by Sturm-sequence

@@ -16,12 +16,15 @@ from .api import (
     apply_H_direct,
     apply_H_sparse,
     build_tables,
+    choose_double_jumps,
     dim,
     hash_batch,
     hash_occ,
+    is_hermitian,
     rho1,
     rho2,
     t2_lookup,
+    tables_bytes,
     tables_size,
     unhash,
     unhash_batch,
@@ -36,5 +39,5 @@ from .propagate import SILStepper, sil_step
 __all__ = [
     "MCError", "LIB_PATH", "SILStepper", "sil_step", "Batch", "BatchedLanczos", "batched_lanczos", "Energy", "DirectSpace", "Tables", "apply_H", "apply_H_adjoint", "apply_H_direct", "apply_H_sparse", "energy", "build_tables", "dim", "hash_batch",
     "hash_occ", "rho1", "rho2", "t2_lookup", "tables_size", "unhash", "unhash_batch",
-    "workspace_size", "zaxpby", "zdotc",
+    "workspace_size", "zaxpby", "zdotc", "choose_double_jumps", "is_hermitian", "tables_bytes",
 ]

@@ -112,6 +112,14 @@ SIGNATURES = {
     "mc_rho2_direct": (ctypes.c_int, [c_i32, c_i32, c_p, c_p, c_p, c_sz, c_p]),
     "mc_tridiag_expv": (ctypes.c_int, [c_i32, c_p, c_p, ctypes.c_double, c_p]),
     "mc_lanczos_orth": (ctypes.c_int, [c_i64, c_p, c_p, c_p, c_p, c_p, c_p]),
+    "mc_apply_H_direct_adjoint": (ctypes.c_int, [c_i32, c_i32, c_p, c_p, c_p, c_p, c_p, c_sz,
+                                                 c_p]),
+    "mc_is_hermitian": (ctypes.c_int, [c_i32, c_p, c_p, c_p, c_p]),
+    "mc_tables_bytes": (ctypes.c_int, [c_i32, c_i32, c_i32, c_i32, ctypes.POINTER(c_i64)]),
+    "mc_choose_double_jumps": (ctypes.c_int, [c_i32, c_p, c_p, c_i32, ctypes.c_double, c_p]),
+    "mc_sil_coefficients": (ctypes.c_int, [c_i32, c_p, c_p, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_double, c_p, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(c_i32)]),
 }
 
 
@@ -134,6 +142,10 @@ SIGNATURES.update({
     "mc_batch_dot": (ctypes.c_int, [c_p, c_p, c_p, c_p, c_p]),
     "mc_batch_lanczos_orth": (ctypes.c_int, [c_p, c_p, c_p, c_p, c_p, c_p, c_p]),
     "mc_batch_normalize": (ctypes.c_int, [c_p, c_p, c_p, c_p, c_p]),
+    "mc_batch_lanczos_graph": (ctypes.c_int, [c_p, c_i32, c_p, c_p, c_p, c_p, c_p, c_p,
+                                              ctypes.POINTER(c_p)]),
+    "mc_graph_launch": (ctypes.c_int, [c_p, c_p]),
+    "mc_graph_destroy": (ctypes.c_int, [c_p]),
 })
 
 

@@ -69,6 +69,31 @@ def tables_size(N: int, M: int) -> L.TableSizes:
     return s
 
 
+def tables_bytes(N: int, M: int, form: str = "paper", double_jumps: bool = True) -> int:
+    """Device bytes of the tables of (N, M) (the double-jump map at its
+    largest tiled size)."""
+    out = ctypes.c_int64()
+    L.check(L.load().mc_tables_bytes(N, M, L.FORMS[form], int(bool(double_jumps)),
+                                     ctypes.byref(out)), "mc_tables_bytes")
+    return int(out.value)
+
+
+def choose_double_jumps(shapes, budget_bytes: float, form: str = "paper") -> list[bool]:
+    """Which instances [(N, M), ...] keep a double-jump map within
+    `budget_bytes` of map memory (smallest maps first); the rest chain
+    single jumps."""
+    n = len(shapes)
+    Ns = np.ascontiguousarray([s[0] for s in shapes], dtype=np.int32)
+    Ms = np.ascontiguousarray([s[1] for s in shapes], dtype=np.int32)
+    keep = np.zeros(n, dtype=np.int32)
+    L.check(L.load().mc_choose_double_jumps(n, Ns.ctypes.data_as(ctypes.c_void_p),
+                                            Ms.ctypes.data_as(ctypes.c_void_p), L.FORMS[form],
+                                            float(budget_bytes),
+                                            keep.ctypes.data_as(ctypes.c_void_p)),
+            "mc_choose_double_jumps")
+    return [bool(k) for k in keep]
+
+
 def workspace_size(N: int, M: int, op: int) -> int:
     b = L.c_sz()
     L.check(L.load().mc_workspace_size(N, M, op, ctypes.byref(b)), "mc_workspace_size")
@@ -307,12 +332,9 @@ def apply_H_direct(h, g, C: torch.Tensor, N: int, M: int,
     return out
 
 
-def apply_H_adjoint(h, g, C: torch.Tensor, tables: Tables,
-                    out: torch.Tensor | None = None) -> torch.Tensor:
-    """H^dagger . C (h -> h^dagger, g_ksql -> conj(g_lqsk))."""
-    if isinstance(tables, DirectSpace):
-        raise ValueError("the adjoint apply needs tables (for Hermitian h and g, "
-                         "H^dagger C = H C: use apply_H)")
+def apply_H_adjoint(h, g, C: torch.Tensor, tables, out: torch.Tensor | None = None) -> torch.Tensor:
+    """H^dagger . C (h -> h^dagger, g_ksql -> conj(g_lqsk)), through the jump
+    maps (Tables) or table-free (DirectSpace)."""
     N, M, dev = tables.N, tables.M, tables.device
     h = _as_dev(h, dev, (M, M))
     g = _as_dev(g, dev, (M, M, M, M))
@@ -322,10 +344,27 @@ def apply_H_adjoint(h, g, C: torch.Tensor, tables: Tables,
     _require(out, "out", torch.complex128, dev, numel=tables.dim)
     ws = tables.workspace(L.MC_OP_APPLY)
     with torch.cuda.device(dev):
-        L.check(L.load().mc_apply_H_adjoint(N, M, _ptr(h), _ptr(g), ctypes.byref(tables.c),
-                                            _ptr(C), _ptr(out), _ptr(ws), ws.numel(),
-                                            _stream(dev)), "mc_apply_H_adjoint")
+        if isinstance(tables, DirectSpace):
+            L.check(L.load().mc_apply_H_direct_adjoint(N, M, _ptr(h), _ptr(g), _ptr(C), _ptr(out),
+                                                       _ptr(ws), ws.numel(), _stream(dev)),
+                    "mc_apply_H_direct_adjoint")
+        else:
+            L.check(L.load().mc_apply_H_adjoint(N, M, _ptr(h), _ptr(g), ctypes.byref(tables.c),
+                                                _ptr(C), _ptr(out), _ptr(ws), ws.numel(),
+                                                _stream(dev)), "mc_apply_H_adjoint")
     return out
+
+
+def is_hermitian(h, g, M: int, device) -> bool:
+    """True if h = h^dagger and g_ksql = conj(g_lqsk) elementwise (then
+    H^dagger = H); one small kernel and a 4-byte read back."""
+    h = _as_dev(h, device, (M, M))
+    g = _as_dev(g, device, (M, M, M, M))
+    flag = torch.empty(1, dtype=torch.int32, device=device)
+    with torch.cuda.device(device):
+        L.check(L.load().mc_is_hermitian(M, _ptr(h), _ptr(g), _ptr(flag), _stream(device)),
+                "mc_is_hermitian")
+    return bool(flag.item())
 
 
 def zaxpby(x: torch.Tensor, a: torch.Tensor | None = None, y: torch.Tensor | None = None,

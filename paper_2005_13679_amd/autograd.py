@@ -6,9 +6,11 @@ conjugate-Wirtinger convention, upstream gradient gbar = dL/dE*):
     grad_h = gbar conj(rho1),           rho1_kl = <a+_k a_l>        (Eq. rho1)
     grad_g = gbar (1/2) conj(rho2),     rho2_ksql = <a+_k a+_s a_q a_l> (Eq. rho2)
 since E = sum_kl h_kl rho1_kl + 1/2 sum g_ksql rho2_ksql is linear in h and g
-and sesquilinear in C.  For Hermitian h, g (the default assumption) H^dagger C
-is the saved H C, so dC costs no extra pass; otherwise one adjoint apply.
-All arithmetic runs in the library's kernels.
+and sesquilinear in C.  When H^dagger = H, H^dagger C is the saved H C and dC
+costs no extra pass; otherwise it takes one adjoint apply.  ``hermitian=None``
+(the default) decides on the device (mc_is_hermitian: h = h^dagger and
+g_ksql = conj(g_lqsk) elementwise); True or False skips the check.  All
+arithmetic runs in the library's kernels.
 """
 
 from __future__ import annotations
@@ -20,10 +22,12 @@ from . import api
 
 class Energy(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, C, h, g, tables, hermitian=True):
+    def forward(ctx, C, h, g, tables, hermitian=None):
         M = tables.M
         h = h.reshape(M, M).contiguous()
         g = g.reshape(M, M, M, M).contiguous()
+        if hermitian is None:
+            hermitian = api.is_hermitian(h, g, M, C.device)
         HC = api.apply_H(h, g, C, tables)
         E = api.zdotc(C, HC)
         ctx.save_for_backward(C, HC, h, g)
@@ -49,5 +53,5 @@ class Energy(torch.autograd.Function):
         return grad_C, grad_h, grad_g, None, None
 
 
-def energy(C, h, g, tables, hermitian=True):
+def energy(C, h, g, tables, hermitian=None):
     return Energy.apply(C, h, g, tables, hermitian)

@@ -9,7 +9,7 @@ the order the instances were given (``Batch.offsets``).
 from __future__ import annotations
 
 import ctypes
-import math
+import weakref
 
 import numpy as np
 import torch
@@ -19,33 +19,16 @@ from . import api
 
 
 def table_bytes(N: int, M: int, double_jumps: bool, form: str = "paper") -> int:
-    """Device bytes of the tables of one instance (double-jump map included
-    only if requested; its tiled size is estimated as the packed size plus an
-    eighth of a 64-row block per pair and tile for padding)."""
-    s = api.tables_size(N, M)
-    b = s.binom_bytes + s.occ_bytes_total + s.t1_bytes + s.pmask_bytes + s.t2_off_bytes
-    if double_jumps:
-        if form == "reduced":
-            per_tile = M * (M * (M - 1) // 2) + (M * (M - 1) // 2) * ((M - 1) * (M - 2) // 2)
-            b += 4 * s.t2r_compact_entries + 4 * s.tiles * per_tile * 64 // 8
-        else:
-            b += 4 * s.t2_compact_entries + 4 * s.tiles * (M * (M + 1) // 2) * M * M * 64 // 8
-    return int(b)
+    """Device bytes of the tables of one instance (mc_tables_bytes: the
+    double-jump map, if requested, at its largest tiled size)."""
+    return api.tables_bytes(N, M, form, double_jumps)
 
 
 def choose_double_jumps(shapes, budget_bytes: float, form: str = "paper") -> list[bool]:
     """Which instances keep a double-jump map within `budget_bytes` of
-    double-jump tables: smallest maps first (most instances served); the rest
-    chain single jumps."""
-    sizes = [(table_bytes(N, M, True, form) - table_bytes(N, M, False, form), i)
-             for i, (N, M) in enumerate(shapes)]
-    use = [False] * len(shapes)
-    left = float(budget_bytes)
-    for sz, i in sorted(sizes):
-        if sz <= left:
-            use[i] = True
-            left -= sz
-    return use
+    double-jump tables (mc_choose_double_jumps: smallest maps first, so the
+    most instances are served); the rest chain single jumps."""
+    return api.choose_double_jumps(shapes, budget_bytes, form)
 
 
 class Batch:
@@ -88,16 +71,12 @@ class Batch:
                                         self.plan.numel(), api._stream(self.device),
                                         ctypes.byref(handle)), "mc_batch_create")
         self._h = handle
+        # destroy the host handle when the batch is collected (or at exit)
+        self._finalizer = weakref.finalize(self, lib.mc_batch_destroy, handle)
         self.count = n
         self.length = int(lib.mc_batch_vector_length(handle))
         dims = [t.dim for t in self.tables]
         self.offsets = np.concatenate([[0], np.cumsum(dims)]).astype(np.int64)
-
-    def __del__(self):
-        h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            L.load().mc_batch_destroy(h)
-            self._h = None
 
     def vector(self) -> torch.Tensor:
         return torch.empty(self.length, dtype=torch.complex128, device=self.device)
@@ -142,14 +121,15 @@ class Batch:
 
 class BatchedLanczos:
     """Fixed-length three-term Lanczos recurrence (no reorthogonalisation) for
-    every instance of a batch; ``graph=True`` captures all steps into one HIP
-    graph that is replayed by ``run``."""
+    every instance of a batch; ``graph=True`` has the library capture all
+    steps into one HIP graph (mc_batch_lanczos_graph) that ``run`` replays."""
 
     def __init__(self, batch: Batch, steps: int = 50, graph: bool = True):
         self.b, self.steps = batch, int(steps)
         dev = batch.device
         self.v_in = batch.vector()
-        self.V = [batch.vector() for _ in range(3)]
+        self.Vbuf = torch.empty((3, batch.length), dtype=torch.complex128, device=dev)
+        self.V = [self.Vbuf[i] for i in range(3)]
         self.w = batch.vector()
         self.alphas = torch.zeros((self.steps, batch.count), dtype=torch.complex128, device=dev)
         self.betas = torch.zeros((self.steps + 1, batch.count), dtype=torch.float64, device=dev)
@@ -158,14 +138,16 @@ class BatchedLanczos:
             # warm up outside capture (first launches load code objects)
             self._record()
             torch.cuda.synchronize(dev)
-            g = torch.cuda.CUDAGraph()
-            s = torch.cuda.Stream(device=dev)
-            s.wait_stream(torch.cuda.current_stream(dev))
-            with torch.cuda.stream(s):
-                with torch.cuda.graph(g, stream=s):
-                    self._record()
-            torch.cuda.current_stream(dev).wait_stream(s)
-            self.graph = g
+            self.stream = torch.cuda.Stream(device=dev)
+            handle = ctypes.c_void_p()
+            lib = L.load()
+            P = api._ptr
+            L.check(lib.mc_batch_lanczos_graph(batch._h, self.steps, P(self.v_in), P(self.Vbuf),
+                                               P(self.w), P(self.alphas), P(self.betas),
+                                               ctypes.c_void_p(self.stream.cuda_stream),
+                                               ctypes.byref(handle)), "mc_batch_lanczos_graph")
+            self.graph = handle
+            self._finalizer = weakref.finalize(self, lib.mc_graph_destroy, handle)
 
     def _record(self):
         b, V, w = self.b, self.V, self.w
@@ -182,12 +164,17 @@ class BatchedLanczos:
         """Runs the recurrence from the batch vector v0; returns (alphas
         [steps, count] real, betas [steps, count]) as host arrays."""
         self.b._chk(v0, "v0")
+        dev = self.b.device
         self.v_in.copy_(v0)
         if self.graph is not None:
-            self.graph.replay()
+            cur = torch.cuda.current_stream(dev)
+            self.stream.wait_stream(cur)
+            L.check(L.load().mc_graph_launch(self.graph, ctypes.c_void_p(self.stream.cuda_stream)),
+                    "mc_graph_launch")
+            cur.wait_stream(self.stream)
         else:
             self._record()
-        torch.cuda.synchronize(self.b.device)
+        torch.cuda.synchronize(dev)
         return (self.alphas.real.cpu().numpy().copy(), self.betas[: self.steps].cpu().numpy().copy())
 
 

@@ -705,4 +705,79 @@ int mc_batch_normalize(const mc_batch *b, const double *w_d, double *out_d, doub
     return launch_status();
 }
 
+struct mc_graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+int mc_batch_lanczos_graph(const mc_batch *b, int32_t steps, const double *v0_d, double *V_d,
+                           double *w_d, double *alpha_d, double *beta_d, mc_stream stream,
+                           mc_graph **out)
+{
+    if (!b || steps < 1 || !v0_d || !V_d || !w_d || !alpha_d || !beta_d || !out || !stream)
+        return MC_EINVAL;
+    *out = nullptr;
+    const int64_t n = b->total_len;
+    double *V[3] = {V_d, V_d + 2 * n, V_d + 4 * n};
+    for (int i = 0; i < 3; ++i)
+        if (overlaps(V[i], (size_t)n * 16, w_d, (size_t)n * 16)) return MC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    int st = set_hip_error(hipStreamIsCapturing(s, &cs));
+    if (st) return st;
+    if (cs != hipStreamCaptureStatusNone) return MC_EINVAL;
+    st = set_hip_error(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    if (st) return st;
+    // the recurrence; every call below only enqueues kernels
+    int rec = mc_batch_normalize(b, v0_d, V[0], beta_d + (int64_t)steps * b->count, stream);
+    for (int32_t j = 0; j < steps && rec == MC_OK; ++j) {
+        double *cur = V[j % 3], *prev = V[(j + 2) % 3], *nxt = V[(j + 1) % 3];
+        double *alpha_j = alpha_d + (int64_t)2 * j * b->count;
+        rec = mc_batch_apply_H(b, cur, w_d, stream);
+        if (rec == MC_OK) rec = mc_batch_dot(b, cur, w_d, alpha_j, stream);
+        if (rec == MC_OK)
+            rec = mc_batch_lanczos_orth(b, w_d, cur, j > 0 ? prev : nullptr, alpha_j,
+                                        j > 0 ? beta_d + (int64_t)(j - 1) * b->count : nullptr,
+                                        stream);
+        if (rec == MC_OK) rec = mc_batch_normalize(b, w_d, nxt, beta_d + (int64_t)j * b->count, stream);
+    }
+    hipGraph_t graph = nullptr;
+    st = set_hip_error(hipStreamEndCapture(s, &graph));
+    if (rec != MC_OK || st != MC_OK) {
+        if (graph) hipGraphDestroy(graph);
+        return rec != MC_OK ? rec : st;
+    }
+    hipGraphExec_t exec = nullptr;
+    st = set_hip_error(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    if (st) {
+        hipGraphDestroy(graph);
+        return st;
+    }
+    mc_graph *gr = (mc_graph *)malloc(sizeof(mc_graph));
+    if (!gr) {
+        hipGraphExecDestroy(exec);
+        hipGraphDestroy(graph);
+        return MC_ENOMEM;
+    }
+    gr->graph = graph;
+    gr->exec = exec;
+    *out = gr;
+    return MC_OK;
+}
+
+int mc_graph_launch(const mc_graph *g, mc_stream stream)
+{
+    if (!g) return MC_EINVAL;
+    return set_hip_error(hipGraphLaunch(g->exec, (hipStream_t)stream));
+}
+
+int mc_graph_destroy(mc_graph *g)
+{
+    if (!g) return MC_OK;
+    int st = set_hip_error(hipGraphExecDestroy(g->exec));
+    const int st2 = set_hip_error(hipGraphDestroy(g->graph));
+    free(g);
+    return st ? st : st2;
+}
+
 }  // extern "C"

@@ -3,6 +3,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
+#include <utility>
 #include <vector>
 
 #include "mc_internal.h"
@@ -161,6 +163,52 @@ int mc_tables_size(int32_t N, int32_t M, mc_table_sizes *out)
     return MC_OK;
 }
 
+// Device bytes of one instance's tables: the sizes above, plus, with the
+// double-jump map, its tiled size when every tile holds a block for every
+// removal pair (the most it can take: a tile holds a pair's block when any
+// of its rows can lose that pair).
+int mc_tables_bytes(int32_t N, int32_t M, int32_t form, int32_t with_double_jumps,
+                    int64_t *bytes)
+{
+    if (!bytes) return MC_EINVAL;
+    if (form != MC_FORM_PAPER && form != MC_FORM_REDUCED) return MC_EINVAL;
+    mc_table_sizes sz;
+    const int st = mc_tables_size(N, M, &sz);
+    if (st) return st;
+    int64_t b = sz.binom_bytes + sz.occ_bytes_total + sz.t1_bytes + sz.pmask_bytes +
+                sz.t2_off_bytes;
+    if (with_double_jumps) {
+        const int64_t per_row = form == MC_FORM_REDUCED ? reduced_row_entries(M)
+                                                        : (int64_t)M * M * npairs(M);
+        b += 4 * sz.tiles * kTile * per_row;
+    }
+    *bytes = b;
+    return MC_OK;
+}
+
+int mc_choose_double_jumps(int32_t count, const int32_t *N, const int32_t *M, int32_t form,
+                           double budget_bytes, int32_t *keep)
+{
+    if (count < 0 || (count > 0 && (!N || !M || !keep))) return MC_EINVAL;
+    std::vector<std::pair<int64_t, int32_t>> maps((size_t)count);
+    for (int32_t i = 0; i < count; ++i) {
+        int64_t with = 0, without = 0;
+        int st = mc_tables_bytes(N[i], M[i], form, 1, &with);
+        if (!st) st = mc_tables_bytes(N[i], M[i], form, 0, &without);
+        if (st) return st;
+        maps[(size_t)i] = {with - without, i};
+        keep[i] = 0;
+    }
+    std::sort(maps.begin(), maps.end());   // smallest maps first, ties by position
+    double left = budget_bytes;
+    for (const auto &m : maps) {
+        if ((double)m.first > left) break;
+        keep[m.second] = 1;
+        left -= (double)m.first;
+    }
+    return MC_OK;
+}
+
 // exp(-i T dt) e_0 for the real symmetric tridiagonal T (diagonal alpha[K],
 // off-diagonal beta[K-1]): eigen-decomposition T = Q diag(lambda) Q^T by
 // cyclic Jacobi rotations (each rotation zeroes one off-diagonal element of
@@ -220,6 +268,23 @@ int mc_tridiag_expv(int32_t K, const double *alpha, const double *beta, double d
         y[2 * j] = re;
         y[2 * j + 1] = im;
     }
+    return MC_OK;
+}
+
+// Coefficients of a Short Iterative Lanczos step from its K Lanczos
+// coefficients: y = exp(-i T_K dt) e_0, coef = |C| y, and the error
+// estimate |C| beta_K |y_{K-1}| (the weight the next Krylov vector would
+// get); a vanishing beta_K means an invariant Krylov space and an exact step.
+int mc_sil_coefficients(int32_t K, const double *alpha, const double *beta, double beta_next,
+                        double norm_c, double dt, double *coef, double *err, int32_t *invariant)
+{
+    if (!coef || !err || !invariant) return MC_EINVAL;
+    const int st = mc_tridiag_expv(K, alpha, beta, dt, coef);
+    if (st) return st;
+    const double last = hypot(coef[2 * (K - 1)], coef[2 * (K - 1) + 1]);
+    *invariant = beta_next < 1e-14 * fmax(1.0, fabs(alpha[K - 1])) ? 1 : 0;
+    *err = *invariant ? 0.0 : norm_c * beta_next * last;
+    for (int i = 0; i < 2 * K; ++i) coef[i] *= norm_c;
     return MC_OK;
 }
 

@@ -817,6 +817,33 @@ __global__ __launch_bounds__(256) void k_lanczos_orth(int64_t n, double2 *__rest
     }
 }
 
+// flag[0] = 1 if h_kl == conj(h_lk) and g_ksql == conj(g_lqsk) for every
+// index (exact comparisons; then H^dagger = H elementwise), else 0.
+__global__ __launch_bounds__(256) void k_is_hermitian(int M, const double2 *__restrict__ h,
+                                                      const double2 *__restrict__ g,
+                                                      int32_t *__restrict__ flag)
+{
+    __shared__ int ok;
+    if (threadIdx.x == 0) ok = 1;
+    __syncthreads();
+    int mine = 1;
+    const int M2 = M * M;
+    for (int e = threadIdx.x; e < M2; e += blockDim.x) {
+        const int k = e / M, l = e % M;
+        const double2 a = h[e], b = h[l * M + k];
+        if (!(a.x == b.x && a.y == -b.y)) mine = 0;
+    }
+    const int M4 = M2 * M2;
+    for (int e = threadIdx.x; e < M4; e += blockDim.x) {
+        const int l = e % M, q = (e / M) % M, s = (e / M2) % M, k = e / (M2 * M);
+        const double2 a = g[e], b = g[((l * M + q) * M + s) * M + k];
+        if (!(a.x == b.x && a.y == -b.y)) mine = 0;
+    }
+    if (!mine) atomicAnd(&ok, 0);
+    __syncthreads();
+    if (threadIdx.x == 0) flag[0] = ok;
+}
+
 }  // namespace mc
 
 using namespace mc;
@@ -1102,9 +1129,9 @@ int mc_apply_H_sparse(int32_t N, int32_t M, const double *h_d, const double *g_d
     return launch_status();
 }
 
-int mc_apply_H_direct(int32_t N, int32_t M, const double *h_d, const double *g_d,
-                      const double *C_d, double *HC_d, void *ws_d, size_t ws_bytes,
-                      mc_stream stream)
+static int apply_direct_common(int32_t N, int32_t M, const double *h_d, const double *g_d,
+                               const double *C_d, double *HC_d, void *ws_d, size_t ws_bytes,
+                               int adjoint, mc_stream stream)
 {
     int st = check_nm(N, M);
     if (st) return st;
@@ -1120,7 +1147,7 @@ int mc_apply_H_direct(int32_t N, int32_t M, const double *h_d, const double *g_d
     if (M >= MC_LDS_ROOTS_FROM && sqb > 65536) return MC_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     double2 *cf = (double2 *)ws_d;
-    hipLaunchKernelGGL(k_prep_split, dim3(4), dim3(256), 0, s, M, 0, (const double2 *)g_d,
+    hipLaunchKernelGGL(k_prep_split, dim3(4), dim3(256), 0, s, M, adjoint, (const double2 *)g_d,
                        (const double2 *)h_d, cf);
     const int64_t tiles = (D + kTile - 1) / kTile;
     const int64_t nblocks = (tiles + 3) / 4;
@@ -1136,6 +1163,29 @@ int mc_apply_H_direct(int32_t N, int32_t M, const double *h_d, const double *g_d
                                kLdsRoots<MT> ? sqb : 0, s, N, nbits, D, tiles, nblocks,
                                (const double2 *)cf, (const double2 *)C_d, (double2 *)HC_d);
     });
+    return launch_status();
+}
+
+int mc_apply_H_direct(int32_t N, int32_t M, const double *h_d, const double *g_d,
+                      const double *C_d, double *HC_d, void *ws_d, size_t ws_bytes,
+                      mc_stream stream)
+{
+    return apply_direct_common(N, M, h_d, g_d, C_d, HC_d, ws_d, ws_bytes, 0, stream);
+}
+
+int mc_apply_H_direct_adjoint(int32_t N, int32_t M, const double *h_d, const double *g_d,
+                              const double *C_d, double *HC_d, void *ws_d, size_t ws_bytes,
+                              mc_stream stream)
+{
+    return apply_direct_common(N, M, h_d, g_d, C_d, HC_d, ws_d, ws_bytes, 1, stream);
+}
+
+int mc_is_hermitian(int32_t M, const double *h_d, const double *g_d, int32_t *flag_d,
+                    mc_stream stream)
+{
+    if (M < 1 || M > MC_MAX_M || !h_d || !g_d || !flag_d) return MC_EINVAL;
+    hipLaunchKernelGGL(k_is_hermitian, dim3(1), dim3(256), 0, (hipStream_t)stream, M,
+                       (const double2 *)h_d, (const double2 *)g_d, flag_d);
     return launch_status();
 }
 

@@ -9,9 +9,10 @@ The basis grows until the a-posteriori error estimate
 below ``tol`` or ``kmax`` is reached.
 
 Every vector operation runs in the library's kernels (mc_apply_H, mc_zdotc,
-mc_zgemv_c / mc_zgemv_sub, mc_normalize, mc_zgemv_n); the k x k exponential is
-the library's host routine mc_tridiag_expv.  alpha and beta are read back
-after each Lanczos step for the error test.
+mc_zgemv_c / mc_zgemv_sub, mc_normalize, mc_zgemv_n); the k x k exponential,
+the scaling by |C| and the error estimate are the library's host routine
+mc_sil_coefficients.  alpha and beta are read back after each Lanczos step
+for the stopping test.
 """
 
 from __future__ import annotations
@@ -36,6 +37,24 @@ def tridiag_expv(alphas, betas, dt: float) -> np.ndarray:
                                      b.ctypes.data_as(ctypes.c_void_p), float(dt),
                                      y.ctypes.data_as(ctypes.c_void_p)), "mc_tridiag_expv")
     return y[0::2] + 1j * y[1::2]
+
+
+def sil_coefficients(alphas, betas, beta_next: float, norm_c: float, dt: float):
+    """(coefficients |C| exp(-i T dt) e_0 as complex128, error estimate,
+    invariant-space flag) from the library (host routine)."""
+    a = np.ascontiguousarray(alphas, dtype=np.float64)
+    b = np.ascontiguousarray(betas, dtype=np.float64)
+    if b.size < max(0, a.size - 1):
+        raise ValueError("need K-1 off-diagonal entries")
+    coef = np.empty(2 * a.size, dtype=np.float64)
+    err = ctypes.c_double()
+    inv = ctypes.c_int32()
+    L.check(L.load().mc_sil_coefficients(a.size, a.ctypes.data_as(ctypes.c_void_p),
+                                         b.ctypes.data_as(ctypes.c_void_p), float(beta_next),
+                                         float(norm_c), float(dt),
+                                         coef.ctypes.data_as(ctypes.c_void_p), ctypes.byref(err),
+                                         ctypes.byref(inv)), "mc_sil_coefficients")
+    return coef.view(np.complex128), float(err.value), bool(inv.value)
 
 
 class SILStepper:
@@ -81,7 +100,7 @@ class SILStepper:
             out.copy_(C)
             return out, 0, 0.0
         alphas, betas = [], []
-        y, err, m = None, float("inf"), 0
+        coef, err, m = None, float("inf"), 0
         for j in range(cap):
             api.apply_H(self.h, self.g, V[j], self.t, out=w)
             api.zdotc(V[j], w, out=self.alpha_d)
@@ -96,15 +115,11 @@ class SILStepper:
             alphas.append(float(self.alpha_d.real.item()))
             b = float(self.beta_d.item())
             m = j + 1
-            y = tridiag_expv(alphas, betas, dt)
-            err = norm_c * b * abs(y[-1])
-            if b < 1e-14 * max(1.0, abs(alphas[-1])):   # invariant subspace: exact
-                err = 0.0
-                break
-            if k is None and err < tol:
+            coef, err, invariant = sil_coefficients(alphas, betas, b, norm_c, dt)
+            if invariant or (k is None and err < tol):
                 break
             betas.append(b)
-        coef = torch.from_numpy(np.ascontiguousarray(norm_c * y)).to(dev)
+        coef = torch.from_numpy(np.ascontiguousarray(coef)).to(dev)
         with torch.cuda.device(dev):
             L.check(lib.mc_zgemv_n(m, D, P(V), D, P(coef), P(out), st), "mc_zgemv_n")
         return out, m, err

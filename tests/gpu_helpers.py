@@ -80,3 +80,51 @@ def tiled_t2_check_and_rows(tables, rows):
                 assert np.all(blk == -1), ("padding", g, p)
         out.append(np.concatenate(ent) if ent else np.zeros(0, np.int32))
     return out
+
+
+def sampled_tables(tables, rows):
+    """Occupations, single-jump rows and double-jump rows (per-row layout of
+    the tables' form, as returned by the oracle) of the given rows only,
+    gathered on the device: the tiled double-jump map is never copied whole.
+    Also asserts that the tile's blocks of removal pairs a row cannot lose
+    hold -1."""
+    import torch
+
+    M = tables.M
+    P = M * (M + 1) // 2
+    W = (P + 63) // 64
+    rows = np.asarray(rows, dtype=np.int64)
+    tiles, lanes = rows // TILE, rows % TILE
+    dev = tables.t1.device
+    ti, la = torch.from_numpy(tiles).to(dev), torch.from_numpy(lanes).to(dev)
+    occ_t = tables.occ if tables.occ.dtype == torch.uint8 else tables.occ.view(torch.int16)
+    o = occ_t.reshape(tables.tiles, M, TILE)[ti, :, la].cpu().numpy().astype(np.int64)
+    if tables.occ.dtype != torch.uint8:
+        o &= 0xFFFF
+    t1 = tables.t1.reshape(tables.tiles, M, M, TILE)[ti, :, :, la].cpu().numpy()
+    if tables.t2 is None:
+        return o, t1, None
+    slots = np.array([pair_slots(M, k, s, tables.form) for k, s in pair_list(M)], dtype=np.int64)
+    pm_words = tables.pmask.reshape(tables.tiles, W)[ti].cpu().numpy().view(np.uint64)
+    off = tables.t2_off[ti].cpu().numpy()
+    idx, owner, valid_flag = [], [], []
+    for r in range(rows.size):
+        base = off[r]
+        for p, (k, s) in enumerate(pair_list(M)):
+            if not (int(pm_words[r, p // 64]) >> (p % 64)) & 1:
+                continue
+            blk = base + lanes[r] + np.arange(slots[p]) * TILE
+            n = o[r]
+            ok = (n[k] >= 2) if k == s else (n[k] >= 1 and n[s] >= 1)
+            idx.append(blk)
+            owner.append(np.full(slots[p], r))
+            valid_flag.append(np.full(slots[p], ok))
+            base += slots[p] * TILE
+    idx = np.concatenate(idx)
+    owner = np.concatenate(owner)
+    valid_flag = np.concatenate(valid_flag)
+    ent = tables.t2[torch.from_numpy(idx).to(dev)].cpu().numpy()
+    assert np.all(ent[~valid_flag] == -1), "padding of removal pairs a row cannot lose"
+    counts = np.bincount(owner[valid_flag], minlength=rows.size)
+    per_row = np.split(ent[valid_flag], np.cumsum(counts)[:-1])
+    return o, t1, per_row

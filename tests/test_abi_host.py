@@ -206,3 +206,57 @@ def test_tridiag_expv_rejects_bad_sizes(lib):
     a = np.zeros(1)
     assert lib.mc_tridiag_expv(0, a.ctypes.data, None, 0.1, y.ctypes.data) == -1
     assert lib.mc_tridiag_expv(513, a.ctypes.data, a.ctypes.data, 0.1, y.ctypes.data) == -1
+
+
+def test_sil_coefficients_scale_error_and_invariant_space():
+    """mc_sil_coefficients: |C| exp(-i T dt) e_0, the error estimate
+    |C| beta_K |y_{K-1}| and the invariant-space test, against scipy."""
+    from scipy.linalg import expm
+    from paper_2005_13679_amd.propagate import sil_coefficients
+    rng = np.random.default_rng(4)
+    K = 6
+    a = rng.standard_normal(K)
+    b = np.abs(rng.standard_normal(K - 1))
+    T = np.diag(a) + np.diag(b, 1) + np.diag(b, -1)
+    dt, norm_c, beta_next = 0.3, 2.5, 0.7
+    coef, err, inv = sil_coefficients(a, b, beta_next, norm_c, dt)
+    y = expm(-1j * dt * T)[:, 0]
+    assert np.max(np.abs(coef - norm_c * y)) <= 1e-13 * norm_c
+    assert abs(err - norm_c * beta_next * abs(y[-1])) <= 1e-14 * norm_c
+    assert not inv
+    coef0, err0, inv0 = sil_coefficients(a, b, 1e-16, norm_c, dt)
+    assert inv0 and err0 == 0.0 and np.array_equal(coef0, coef)
+
+
+def test_tables_bytes_and_double_jump_budget(lib):
+    import paper_2005_13679_amd as mc
+    for N, M in [(10, 5), (200, 5), (50, 6), (40, 8)]:
+        s = mc.tables_size(N, M)
+        base = s.binom_bytes + s.occ_bytes_total + s.t1_bytes + s.pmask_bytes + s.t2_off_bytes
+        assert mc.tables_bytes(N, M, "paper", False) == base
+        full_p = M * M * (M * (M + 1) // 2)
+        full_r = M * (M * (M - 1) // 2) + (M * (M - 1) // 2) * ((M - 1) * (M - 2) // 2)
+        assert mc.tables_bytes(N, M, "paper", True) == base + 4 * 64 * s.tiles * full_p
+        assert mc.tables_bytes(N, M, "reduced", True) == base + 4 * 64 * s.tiles * full_r
+        # the largest tiled size bounds the packed entries
+        assert 4 * 64 * s.tiles * full_r >= 4 * s.t2r_compact_entries
+    shapes = [(30, 6), (8, 3), (40, 8), (12, 5), (8, 3)]
+    maps = [mc.tables_bytes(N, M, "reduced", True) - mc.tables_bytes(N, M, "reduced", False)
+            for N, M in shapes]
+    for budget in (0.0, maps[1] + 0.5, maps[1] * 2, sum(maps) - 1, sum(maps)):
+        keep = mc.choose_double_jumps(shapes, budget, "reduced")
+        # smallest first, ties by position, stop at the first that does not fit
+        want, left = [False] * len(shapes), budget
+        for sz, i in sorted((m, i) for i, m in enumerate(maps)):
+            if sz > left:
+                break
+            want[i], left = True, left - sz
+        assert keep == want
+        assert sum(m for m, k in zip(maps, keep) if k) <= budget
+    assert mc.choose_double_jumps(shapes, 1e30, "reduced") == [True] * len(shapes)
+    keep = (ctypes.c_int32 * 1)()
+    n = (ctypes.c_int32 * 1)(40)
+    m = (ctypes.c_int32 * 1)(30)
+    assert lib.mc_choose_double_jumps(1, n, m, 1, 1e9, keep) == -2    # D >= 2^31
+    out = ctypes.c_int64()
+    assert lib.mc_tables_bytes(10, 5, 7, 1, ctypes.byref(out)) == -1  # unknown form

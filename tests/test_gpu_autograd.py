@@ -16,7 +16,11 @@ def dev(x):
     return torch.from_numpy(np.ascontiguousarray(x)).cuda()
 
 
-def fd_check(mc, tab, C, h, g, hermitian, rng, ndir=4, eps=1e-6):
+def fd_check(mc, tab, C, h, g, hermitian, rng, ndir=4, eps=1e-6, kinds=None):
+    """Central differences of Re E along seeded directions of C, h and g
+    against Re <grad, d>.  `kinds` maps an input to its direction kinds:
+    "any" (complex normal entries) or, for h, "hermitian" ((A + A^H) / 2);
+    C directions are unit vectors."""
     Cd = dev(C).requires_grad_(True)
     hd = dev(h).requires_grad_(True)
     gd = dev(g).requires_grad_(True)
@@ -29,10 +33,15 @@ def fd_check(mc, tab, C, h, g, hermitian, rng, ndir=4, eps=1e-6):
         with torch.no_grad():
             return mc.energy(dev(Cx), dev(hx), dev(gx), tab, hermitian).real.item()
 
-    for name in ("C", "h", "g"):
+    kinds = kinds or {"C": ["any"], "h": ["any"], "g": ["any"]}
+    for name, kind in ((n, k) for n in ("C", "h", "g") for k in kinds[n]):
         x0 = base[name]
         for _ in range(ndir):
             d = rng.standard_normal(x0.shape) + 1j * rng.standard_normal(x0.shape)
+            if kind == "hermitian":
+                d = 0.5 * (d + d.conj().T)
+            if name == "C":
+                d /= np.linalg.norm(d)
             args_p = dict(base)
             args_m = dict(base)
             args_p[name] = x0 + eps * d
@@ -77,33 +86,39 @@ def test_gradcheck_tiny(mc):
     assert torch.autograd.gradcheck(f, inputs, eps=1e-6, atol=1e-7, rtol=1e-6)
 
 
-def test_autograd_workload_sampled(mc, oracle_native):
-    """N = 50, M = 6 (dim 3,478,761): rho-gradients vs oracle, C-gradient vs 2HC
-    on sampled rows, and finite differences along seeded directions."""
+@pytest.mark.parametrize("space", ["paper", "direct"])
+def test_autograd_workload(mc, oracle_native, space):
+    """N = 50, M = 6 (dim 3,478,761): the h-gradient against the oracle's
+    rho1, the C-gradient against 2 HC on sampled rows, and central
+    differences along 8 seeded directions each of C, of h (Hermitian-
+    preserving and arbitrary) and of g.  The g-gradient against every
+    rho2 element is in the density-matrix tests."""
     N, M = 50, 6
     C, h, g = W.random_instance(N, M, 3)
-    tab = mc.build_tables(N, M)
-    Cd = dev(C).requires_grad_(True)
-    hd = dev(h).requires_grad_(True)
-    gd = dev(g).requires_grad_(True)
-    E = mc.energy(Cd, hd, gd, tab)
-    E.real.backward()
-    assert rel_inf(hd.grad.cpu().numpy(), np.conj(oracle_native.rho1(N, M, C))) <= 1e-12
-    rows = np.random.default_rng(5).integers(0, tab.dim, 1500)
+    tab = mc.DirectSpace(N, M) if space == "direct" else mc.build_tables(N, M)
+    grads = fd_check(mc, tab, C, h, g, None, np.random.default_rng(6), ndir=8,
+                     kinds={"C": ["any"], "h": ["hermitian", "any"], "g": ["any"]})
+    assert rel_inf(grads["h"], np.conj(oracle_native.rho1(N, M, C))) <= 1e-12
+    rows = np.unique(np.concatenate([np.random.default_rng(5).integers(0, tab.dim, 4000),
+                                     np.arange(64), tab.dim - 1 - np.arange(64)]))
     ref = 2 * oracle_native.apply_h(N, M, h, g, C, rows)
-    assert rel_inf(Cd.grad[torch.from_numpy(rows).cuda()].cpu().numpy(), ref) <= 1e-12
-    idx = np.array([0, 7, 100, 777, M ** 4 - 1])
-    r2 = oracle_native.rho2_elements(N, M, C, idx)
-    assert np.max(np.abs(gd.grad.reshape(-1).cpu().numpy()[idx] - 0.5 * np.conj(r2))) <= 1e-12 * np.max(np.abs(gd.grad.cpu().numpy()))
-    rng = np.random.default_rng(6)
-    eps = 1e-6
-    for _ in range(3):
-        d = W.random_coefficients(rng, tab.dim)
-        with torch.no_grad():
-            ep = mc.energy(dev(C + eps * d), hd, gd, tab).real.item()
-            em = mc.energy(dev(C - eps * d), hd, gd, tab).real.item()
-        fd = (ep - em) / (2 * eps)
-        an = float(np.real(np.vdot(Cd.grad.cpu().numpy(), d)))
-        assert abs(fd - an) <= 1e-6 * max(1.0, abs(an))
+    assert rel_inf(grads["C"][rows], ref) <= 1e-12
     del tab
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("space", ["paper", "reduced", "direct"])
+def test_default_arguments_detect_non_hermitian_inputs(mc, space):
+    """energy(C, h, g, space) with no `hermitian` argument: non-Hermitian h
+    and g must still give the right C-gradient (conj(gbar) HC + gbar H^dagger C),
+    checked by central differences; Hermitian inputs are recognised."""
+    N, M = 8, 4
+    rng = np.random.default_rng(11)
+    C, h, g = W.random_instance(N, M, 12)
+    tab = mc.DirectSpace(N, M) if space == "direct" else mc.build_tables(N, M, form=space)
+    assert mc.is_hermitian(dev(h), dev(g), M, torch.device("cuda"))
+    hn = h + 0.4j * rng.standard_normal((M, M))
+    gn = g + 0.3 * (rng.standard_normal((M,) * 4) + 1j * rng.standard_normal((M,) * 4))
+    assert not mc.is_hermitian(dev(hn), dev(g), M, torch.device("cuda"))
+    assert not mc.is_hermitian(dev(h), dev(gn), M, torch.device("cuda"))
+    fd_check(mc, tab, C, hn, gn, None, rng, ndir=4)

@@ -209,8 +209,8 @@ def test_direct_density_matrices_match_tables(mc):
 
 def test_direct_energy_gradients(mc):
     """E = <C|HC> on a table-free space: value and every gradient (C, h, g)
-    against the reduced-table run; the non-Hermitian C-gradient needs the
-    adjoint apply, which needs tables, and says so."""
+    against the reduced-table run, with Hermitian inputs and with
+    non-Hermitian ones (the C-gradient then takes the table-free adjoint)."""
     N, M = 12, 5
     C, h, g = W.random_instance(N, M, 71)
     out = []
@@ -223,10 +223,31 @@ def test_direct_energy_gradients(mc):
     assert torch.equal(out[0][1], out[1][1])
     for i in (2, 3):
         assert rel_inf(out[0][i].cpu().numpy(), out[1][i].cpu().numpy()) <= TOL
-    Ct = dev(C).requires_grad_(True)
-    E = mc.energy(Ct, dev(h), dev(g), mc.DirectSpace(N, M), hermitian=False)
-    with pytest.raises(ValueError):
-        E.real.backward()
+    rng = np.random.default_rng(72)
+    hn = h + 0.3j * rng.standard_normal((M, M))
+    gn = g + 0.2 * rng.standard_normal((M,) * 4)
+    grads = []
+    for space in (mc.DirectSpace(N, M), mc.build_tables(N, M, form="reduced")):
+        Ct = dev(C).requires_grad_(True)
+        mc.energy(Ct, dev(hn), dev(gn), space).real.backward()
+        grads.append(Ct.grad)
+    assert torch.equal(grads[0], grads[1])
+
+
+@pytest.mark.parametrize("N,M", [(4, 3), (10, 5), (6, 6), (5, 8)])
+def test_direct_adjoint_matches_oracle(mc, oracle_native, N, M):
+    """Table-free H^dagger C with no symmetry of h or g: the oracle's H with
+    h -> h^dagger, g_ksql -> conj(g_lqsk); equal to the reduced-table adjoint."""
+    rng = np.random.default_rng(N * 10 + M + 1)
+    h = rng.standard_normal((M, M)) + 1j * rng.standard_normal((M, M))
+    g = rng.standard_normal((M,) * 4) + 1j * rng.standard_normal((M,) * 4)
+    D = oracle_native.dim(N, M)
+    C = rng.standard_normal(D) + 1j * rng.standard_normal(D)
+    adj = mc.apply_H_adjoint(dev(h), dev(g), dev(C), mc.DirectSpace(N, M))
+    ref = oracle_native.apply_h(N, M, h.conj().T, np.transpose(g, (3, 2, 1, 0)).conj(), C)
+    assert rel_inf(adj.cpu().numpy(), ref) <= TOL
+    tab = mc.apply_H_adjoint(dev(h), dev(g), dev(C), mc.build_tables(N, M, form="reduced"))
+    assert torch.equal(adj, tab)
 
 
 def test_direct_density_matrices_reject_bad_sizes(mc):

@@ -47,21 +47,60 @@ def test_rho_reproducible_and_consistent_with_energy(mc):
     assert abs(E - E2) <= 1e-12 * abs(E)
 
 
-def test_autograd_size_sampled_elements(mc, oracle_native):
-    """N = 50, M = 6 (dim 3,478,761): full rho1, sampled rho2 elements."""
+def unique_rho2_index(M):
+    """Flat indices of rho2_ksql with k <= s and q <= l (the other elements
+    follow from rho_ksql = rho_skql = rho_kslq, exact for bosons)."""
+    return np.array([((k * M + s) * M + q) * M + l for k in range(M) for s in range(k, M)
+                     for q in range(M) for l in range(q, M)], dtype=np.int64)
+
+
+def expand_rho2(M, idx, vals):
+    """Full rho2 from its unique elements through the two pair symmetries."""
+    full = np.full(M ** 4, np.nan + 0j)
+    for t, v in zip(idx, vals):
+        l = t % M
+        q = (t // M) % M
+        s = (t // M ** 2) % M
+        k = t // M ** 3
+        for a, b in ((k, s), (s, k)):
+            for c, d in ((q, l), (l, q)):
+                full[((a * M + b) * M + c) * M + d] = v
+    assert not np.isnan(full.real).any()
+    return full.reshape((M,) * 4)
+
+
+@pytest.fixture(scope="module")
+def autograd_size_reference(oracle_native):
+    """Oracle rho1 (all 36 elements) and the 441 unique rho2 elements at
+    N = 50, M = 6 (dim 3,478,761), seed 3."""
     N, M = 50, 6
     C, _, _ = W.random_instance(N, M, 3)
-    tab = mc.build_tables(N, M)
+    idx = unique_rho2_index(M)
+    print(f"[rho] oracle rho1 and {idx.size} rho2 elements at N={N}, M={M}", flush=True)
+    r1 = oracle_native.rho1(N, M, C)
+    r2u = oracle_native.rho2_elements(N, M, C, idx)
+    return C, r1, idx, r2u
+
+
+@pytest.mark.parametrize("space", ["paper", "reduced", "direct"])
+def test_autograd_size_every_element(mc, autograd_size_reference, space):
+    """N = 50, M = 6: rho1 in full and every unique rho2 element against the
+    oracle (the oracle's largest element as the scale), and all 1296 rho2
+    elements against the oracle's unique ones expanded by the pair
+    symmetries; trace and partial-trace invariants."""
+    N, M = 50, 6
+    C, r1_ref, idx, r2u_ref = autograd_size_reference
+    tab = mc.DirectSpace(N, M) if space == "direct" else mc.build_tables(N, M, form=space)
     Cd = dev(C)
     r1 = mc.rho1(Cd, tab).cpu().numpy()
     r2 = mc.rho2(Cd, tab).cpu().numpy()
     assert abs(np.trace(r1) - N) <= 1e-12 * N
     assert np.allclose(np.einsum("kssl->kl", r2), (N - 1) * r1, rtol=0, atol=1e-10)
-    assert rel_inf(r1, oracle_native.rho1(N, M, C)) <= TOL
-    rng = np.random.default_rng(4)
-    idx = np.unique(np.concatenate([rng.integers(0, M ** 4, 12), [0, M ** 4 - 1]]))
-    ref = oracle_native.rho2_elements(N, M, C, idx)
-    assert np.max(np.abs(r2.reshape(-1)[idx] - ref)) <= TOL * np.max(np.abs(r2))
+    assert rel_inf(r1, r1_ref) <= TOL
+    e_u = rel_inf(r2.reshape(-1)[idx], r2u_ref)
+    e_all = rel_inf(r2, expand_rho2(M, idx, r2u_ref))
+    print(f"[rho] {space}: rho2 rel err {e_u:.2e} (unique), {e_all:.2e} (all)", flush=True)
+    assert e_u <= TOL and e_all <= TOL
     del tab
     torch.cuda.empty_cache()
 
