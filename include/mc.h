@@ -212,6 +212,8 @@ int mc_t2_lookup(int32_t N, int32_t M, const mc_tables *t, const int64_t *querie
 #define MC_OP_RHO1  2
 #define MC_OP_RHO2  3
 #define MC_OP_DOT   4
+#define MC_OP_RHO1_DIRECT 5
+#define MC_OP_RHO2_DIRECT 6
 
 /* Bytes of device workspace `op` needs for (N, M) (0 is possible). */
 int mc_workspace_size(int32_t N, int32_t M, int32_t op, size_t *bytes);
@@ -317,16 +319,21 @@ int mc_rho1(int32_t N, int32_t M, const mc_tables *t, const double *C_d,
 int mc_rho2(int32_t N, int32_t M, const mc_tables *t, const double *C_d,
             double *rho2_d, void *ws_d, size_t ws_bytes, mc_stream stream);
 
-/* rho1_d [M*M] (Eq. rho1) and rho2_d [M^4] (Eq. rho2) with no table: each
- * row's occupations and each target configuration computed from the row
- * index in closed form, as in mc_apply_H_direct (a creation into a removed
- * orbital cancels in the closed form, so the coincident-index slots of
- * rho2 need no case analysis; App. B).  rho2 is accumulated over unordered
- * removal pairs and expanded with rho2_ksql = rho2_skql.  1 <= M <= 8,
- * D < 2^31 (MC_ERANGE), (N+3)*8 <= 65536; rho2 also needs 16 D <= 2^32.
- * ws_d: mc_workspace_size(RHO1 / RHO2) bytes (per-wavefront partials,
- * summed in a fixed order: bitwise reproducible).  Results equal mc_rho1 /
- * mc_rho2 up to rounding order. */
+/* rho1_d [M*M] (Eq. rho1) and rho2_d [M^4] (Eq. rho2) with no table, as
+ * Gram matrices over the configurations m of N-1 and N-2 particles:
+ *   rho_kl   = sum_m conj(X1_m[k]) X1_m[l],   X1_m[l] = sqrt(m_l+1) C[m + e_l],
+ *   rho_ksql = sum_m conj(X2_m[ks]) X2_m[ql],
+ *   X2_m[ql] = sqrt((m_q+1)(m_l+1+[q=l])) C[m + e_q + e_l]
+ * (the annihilators of Eqs. rho1, rho2 applied to the ket; ladder
+ * amplitudes of Sec. II).  The index of m + e_q + e_l follows from m's
+ * prefix sums in closed form, as in mc_apply_H_direct.  Only the upper
+ * triangle over unordered pairs is accumulated; the rest follows from
+ * rho_ksql = rho_skql = rho_kslq = conj(rho_qlks) (and rho_lk = conj(rho_kl)),
+ * diagonal entries are real.  N < 1 (rho1) or N < 2 (rho2) gives zeros.
+ * 1 <= M <= 8 (MC_EINVAL), D < 2^31 (MC_ERANGE).  ws_d: at least
+ * mc_workspace_size(MC_OP_RHO1_DIRECT / MC_OP_RHO2_DIRECT) bytes (per-
+ * wavefront partials and their fixed-order sum: bitwise reproducible), else
+ * MC_ENOMEM.  Results equal mc_rho1 / mc_rho2 up to rounding order. */
 int mc_rho1_direct(int32_t N, int32_t M, const double *C_d, double *rho1_d, void *ws_d,
                    size_t ws_bytes, mc_stream stream);
 int mc_rho2_direct(int32_t N, int32_t M, const double *C_d, double *rho2_d, void *ws_d,

@@ -22,6 +22,8 @@ MC_EHIP = -4
 MC_OP_APPLY = 1
 MC_OP_RHO1 = 2
 MC_OP_RHO2 = 3
+MC_OP_RHO1_DIRECT = 5
+MC_OP_RHO2_DIRECT = 6
 MC_OP_DOT = 4
 
 MC_MAX_M = 32

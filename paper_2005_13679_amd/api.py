@@ -239,7 +239,9 @@ class DirectSpace:
         self._ws = None
 
     def workspace(self, op: int) -> torch.Tensor:
-        if op not in (L.MC_OP_APPLY, L.MC_OP_RHO1, L.MC_OP_RHO2):
+        # the table-free density matrices have workspaces of their own
+        op = {L.MC_OP_RHO1: L.MC_OP_RHO1_DIRECT, L.MC_OP_RHO2: L.MC_OP_RHO2_DIRECT}.get(op, op)
+        if op not in (L.MC_OP_APPLY, L.MC_OP_RHO1_DIRECT, L.MC_OP_RHO2_DIRECT):
             raise ValueError("a table-free space supports H.C, rho1 and rho2")
         if self._ws is None:
             self._ws = {}

@@ -17,7 +17,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmc.so")
 
-SOURCES = ["mc_host.hip", "mc_tables.hip", "mc_ops.hip", "mc_batch.hip", "mc_direct_rho.hip"]
+SOURCES = ["mc_host.hip", "mc_tables.hip", "mc_ops.hip", "mc_batch.hip", "mc_gram_direct.hip",
+           "mc_gram_tables.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

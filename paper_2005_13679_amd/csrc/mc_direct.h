@@ -63,6 +63,32 @@ __host__ __device__ constexpr int prefix_delta(int m, int R1, int R2, int A1, in
            (R2 >= 0 && R2 <= m);
 }
 
+// Prefix sums S_0..S_{M-1} of row `row` (0 <= row < D) of the space of N
+// particles: greedily from J = D - 1 - row, S_m = the largest s <= S_{m+1}
+// with G_m(s) <= what is left of J, m = M-2 .. 1, then S_0 = the rest.
+// `nbits` = bit width of N (a wave-uniform trip count for the search).
+template <int MT>
+__device__ __forceinline__ void direct_prefix(int64_t row, int64_t D, int N, int nbits,
+                                              int (&S)[MT])
+{
+    S[MT - 1] = N;
+    double J = (double)(D - 1 - row);
+#pragma unroll
+    for (int m = MT - 2; m >= 1; --m) {
+        // largest s in [0, S_{m+1}] with P_m(s) <= J (m+1)!  (P_m(0) = 0)
+        const double lim = J * direct_fact(m + 1);
+        const int hi = S[m + 1];
+        int s = 0;
+        for (int b = nbits - 1; b >= 0; --b) {
+            const int c = s | (1 << b);
+            if (c <= hi && direct_prod(m, (double)c) <= lim) s = c;
+        }
+        S[m] = s;
+        J -= direct_g(m, (double)s);
+    }
+    if constexpr (MT >= 2) S[0] = (int)J;
+}
+
 // One row: its index, occupations and the target-index increments.
 template <int MT>
 struct DirectRow {
@@ -76,22 +102,7 @@ struct DirectRow {
     {
         g = (uint32_t)row;
         int S[MT];
-        S[MT - 1] = N;
-        double J = (double)(D - 1 - row);
-#pragma unroll
-        for (int m = MT - 2; m >= 1; --m) {
-            // largest s in [0, S_{m+1}] with P_m(s) <= J (m+1)!  (P_m(0) = 0)
-            const double lim = J * direct_fact(m + 1);
-            const int hi = S[m + 1];
-            int s = 0;
-            for (int b = nbits - 1; b >= 0; --b) {
-                const int c = s | (1 << b);
-                if (c <= hi && direct_prod(m, (double)c) <= lim) s = c;
-            }
-            S[m] = s;
-            J -= direct_g(m, (double)s);
-        }
-        if constexpr (MT >= 2) S[0] = (int)J;
+        direct_prefix<MT>(row, D, N, nbits, S);
         n[0] = S[0];
 #pragma unroll
         for (int m = 1; m < MT; ++m) n[m] = S[m] - S[m - 1];

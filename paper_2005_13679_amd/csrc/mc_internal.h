@@ -66,6 +66,15 @@ inline int64_t reduced_row_entries(int M)
            (int64_t)(M * (M - 1) / 2) * (M >= 2 ? reduced_slots(M, 0, 1) : 0);
 }
 
+// Workspace bytes of the table-free density matrices over configurations of
+// N - L particles (L = 1: rho1, L = 2: rho2); 0 if a dimension overflows.
+size_t gram_workspace(int32_t N, int32_t M, int L);
+// The same through the jump maps (rows of the N-particle space).
+size_t gram_table_workspace(int32_t N, int32_t M, int L);
+// rho1 through the single-jump map for M > 8 (run-time orbital count).
+int rho1_generic(int32_t N, int32_t M, const mc_tables *t, const double *C_d, double *rho1_d,
+                 void *ws_d, size_t ws_bytes, mc_stream stream);
+
 // Validates (N, M) ranges; MC_OK or MC_EINVAL.
 int check_nm(int32_t N, int32_t M);
 // D = C(N+M-1, N) with overflow check; -1 on overflow.

@@ -15,6 +15,7 @@
 #include "mc_split.h"
 #include "mc_sparse.h"
 #include "mc_direct.h"
+#include "mc_gram.h"
 #include "mc_internal.h"
 
 namespace mc {
@@ -242,11 +243,12 @@ __global__ __launch_bounds__(64) void k_apply_generic(int M, int64_t D, int64_t 
 }
 
 // ---------------------------------------------------------------------------
-// Density matrices.  Wave w accumulates tiles w, w + nwaves, ... in a fixed
-// order; each per-slot value is summed over the 64 rows of the tile with a
-// butterfly (all lanes receive the total) and lane (e mod 64) keeps element e.
-// Partials per wave go to the workspace and are summed over waves in a fixed
-// order by the finalize kernels: results are bitwise reproducible.
+// rho1 for M > 8 (the Gram kernels of mc_gram.h cover M <= 8).  Wave w
+// accumulates tiles w, w + nwaves, ... in a fixed order; each per-slot value
+// is summed over the 64 rows of the tile with a butterfly (all lanes receive
+// the total) and lane (e mod 64) keeps element e.  Partials per wave go to
+// the workspace ([element][wave]) and are summed over waves by a fixed tree:
+// results are bitwise reproducible.
 // ---------------------------------------------------------------------------
 constexpr int kRhoWaves = 4096;
 
@@ -316,308 +318,8 @@ __global__ __launch_bounds__(256) void k_rho1_generic(int Mrt, int64_t D, int64_
 #pragma unroll (kUnroll<MT>)
     for (int j = 0; j < NA; ++j) {
         const int e = j * 64 + lane;
-        if (e < E) part[(int64_t)wave * E + e] = make_double2(accr[j], acci[j]);
+        if (e < E) part[(int64_t)e * nwaves + wave] = make_double2(accr[j], acci[j]);
     }
-}
-
-// ---------------------------------------------------------------------------
-// Density matrices for M <= 8.  Each wavefront keeps per-lane partial sums
-// over all of its tiles (tiles w, w + nwaves, ...) and reduces across lanes
-// once at the end, so the cross-lane work does not grow with the number of
-// rows.  Square roots of small integers come from an LDS table.
-// ---------------------------------------------------------------------------
-constexpr int kRhoChunk = 32;   // slots accumulated per pass
-
-// Bit p set for the removal pairs p = (k, k) (lexicographic pair order).
-__host__ __device__ constexpr uint64_t diag_pair_mask(int M)
-{
-    uint64_t m = 0;
-    int p = 0;
-    for (int k = 0; k < M; ++k)
-        for (int s = k; s < M; ++s, ++p)
-            if (k == s) m |= (uint64_t)1 << p;
-    return m;
-}
-
-
-// rho1: elements e = k*M + l, chunk [J0, J0 + CH) of them per pass
-template <int MT, typename OccT, bool BIGC, int J0>
-__device__ __forceinline__ void rho1_chunk(int64_t D, int64_t tiles, int nwaves, int wave,
-                                           const OccT *__restrict__ occ,
-                                           const int32_t *__restrict__ t1,
-                                           const Gather<BIGC> &ldc, const double *sq,
-                                           double2 *__restrict__ part)
-{
-    constexpr int NS = MT * MT;
-    constexpr int CH = NS - J0 < kRhoChunk ? NS - J0 : kRhoChunk;
-    const int lane = threadIdx.x & 63;
-    double ar[CH], ai[CH];
-#pragma unroll
-    for (int i = 0; i < CH; ++i) ar[i] = ai[i] = 0.0;
-    for (int64_t tile = wave; tile < tiles; tile += nwaves) {
-        const int64_t g = tile * kTile + lane;
-        int n[MT];
-#pragma unroll
-        for (int m = 0; m < MT; ++m) n[m] = (int)occ[(tile * MT + m) * kTile + lane];
-        const double2 cg = ldc(g < D ? (int32_t)g : -1);
-        const __amdgpu_buffer_rsrc_t r1 =
-            make_rsrc(t1 + tile * NS * kTile, (uint32_t)(NS * kTile * 4));
-        int32_t t[CH];
-        double2 c[CH];
-#pragma unroll
-        for (int i = 0; i < CH; ++i) {
-            const int j = J0 + i, k = j / MT, l = j % MT;
-            if (k != l) t[i] = buf_ld_i32(r1, (uint32_t)((j * kTile + lane) * 4), 0);
-        }
-#pragma unroll
-        for (int i = 0; i < CH; ++i) {
-            const int j = J0 + i, k = j / MT, l = j % MT;
-            if (k != l) c[i] = ldc(t[i]);
-        }
-#pragma unroll
-        for (int i = 0; i < CH; ++i) {
-            const int j = J0 + i, k = j / MT, l = j % MT;
-            if (k == l) {
-                ar[i] = fma(cg.x * cg.x + cg.y * cg.y, (double)n[k], ar[i]);
-            } else {
-                const double f = sq[n[k]] * sq[n[l] + 1];
-                ar[i] = fma((cg.x * c[i].x + cg.y * c[i].y), f, ar[i]);
-                ai[i] = fma((cg.x * c[i].y - cg.y * c[i].x), f, ai[i]);
-            }
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < CH; ++i) {
-        const double vr = wave_sum(ar[i]), vi = wave_sum(ai[i]);
-        if (lane == 0) part[(int64_t)wave * NS + J0 + i] = make_double2(vr, vi);
-    }
-}
-
-template <int MT, typename OccT, bool BIGC, int... Js>
-__device__ __forceinline__ void rho1_all(std::integer_sequence<int, Js...>, int64_t D,
-                                         int64_t tiles, int nwaves, int wave,
-                                         const OccT *__restrict__ occ,
-                                         const int32_t *__restrict__ t1, const Gather<BIGC> &ldc,
-                                         const double *sq, double2 *__restrict__ part)
-{
-    (rho1_chunk<MT, OccT, BIGC, Js * kRhoChunk>(D, tiles, nwaves, wave, occ, t1, ldc, sq, part),
-     ...);
-}
-
-template <int MT, typename OccT, bool BIGC>
-__global__ __launch_bounds__(256) void k_rho1(int N, int64_t D, int64_t tiles, int nwaves,
-                                               const OccT *__restrict__ occ,
-                                               const int32_t *__restrict__ t1,
-                                               const double2 *__restrict__ C,
-                                               double2 *__restrict__ part)
-{
-    extern __shared__ double sq[];
-    fill_sqrt_table(sq, N + 3);
-    const int wave = blockIdx.x * 4 + wave_in_block();
-    if (wave >= nwaves) return;
-    const Gather<BIGC> ldc(C, D);
-    constexpr int NCH = (MT * MT + kRhoChunk - 1) / kRhoChunk;
-    rho1_all<MT, OccT, BIGC>(std::make_integer_sequence<int, NCH>{}, D, tiles, nwaves, wave, occ,
-                             t1, ldc, sq, part);
-}
-
-// rho2 for removal pair p = (k, s) (run-time), slots [J0, J0 + CH) of its
-// M*M creation pairs (compile-time).  The occupations of the lane's row are
-// also kept in LDS (occ_lds[m][lane]) so n_k, n_s need no register indexing.
-// RED: tables in the reduced form; a slot's configuration is then the row
-// itself ({q,l} = {k,s}), a single jump (one shared orbital: the unmatched
-// removal a and creation b give T1[a][b]) or a reduced-map entry.
-template <int MT, typename OccT, bool RED, int J0>
-__device__ __forceinline__ void rho2_chunk(int k, int s, int p, int64_t D, int64_t tiles,
-                                           int nwaves, int wave, int64_t cap,
-                                           const OccT *__restrict__ occ,
-                                           const int32_t *__restrict__ t1,
-                                           const uint64_t *__restrict__ pmask,
-                                           const int64_t *__restrict__ t2_off,
-                                           const int32_t *__restrict__ t2,
-                                           const Gather<false> &ldc, const double *sq,
-                                           int *occ_lds, double2 *__restrict__ part)
-{
-    constexpr int NS = MT * MT;
-    constexpr int NP = MT * (MT + 1) / 2;
-    constexpr int W = (NP + 63) / 64;
-    constexpr int CH = NS - J0 < kRhoChunk ? NS - J0 : kRhoChunk;
-    const int lane = threadIdx.x & 63;
-    double ar[CH], ai[CH];
-#pragma unroll
-    for (int i = 0; i < CH; ++i) ar[i] = ai[i] = 0.0;
-    for (int64_t tile = wave; tile < tiles; tile += nwaves) {
-        const uint64_t *pm = pmask + tile * W;
-        if (!((pm[p >> 6] >> (p & 63)) & 1)) continue;   // no row of the tile can lose (k, s)
-        // slots of the blocks before p's in this tile
-        int64_t before = 0;
-        if constexpr (RED) {
-            // block sizes depend only on k == s: count the present pairs
-            // before p of each kind (pair bits of k == s in kDiag)
-            static_assert(NP <= 64, "one mask word");
-            constexpr uint64_t kDiag = diag_pair_mask(MT);
-            const uint64_t below = pm[0] & (((uint64_t)1 << p) - 1);
-            before = (int64_t)__popcll(below & kDiag) * reduced_slots(MT, 0, 0) +
-                     (int64_t)__popcll(below & ~kDiag) * (MT >= 2 ? reduced_slots(MT, 0, 1) : 0);
-        } else {
-#pragma unroll
-            for (int wd = 0; wd < W; ++wd) {
-                const uint64_t word = pm[wd];
-                if (wd < (p >> 6)) before += __popcll(word);
-                else if (wd == (p >> 6)) before += __popcll(word & (((uint64_t)1 << (p & 63)) - 1));
-            }
-            before *= NS;
-        }
-        const int BS = RED ? reduced_slots(MT, k, s) : NS;
-        int64_t off0, off1;
-        t2_block(t2_off, tile, cap, off0, off1);
-        const int64_t bs = off0 + before * kTile;
-        if (bs + (int64_t)BS * kTile > off1) continue;
-        const __amdgpu_buffer_rsrc_t r2 = make_rsrc(t2 + bs, (uint32_t)(BS * kTile * 4));
-        const __amdgpu_buffer_rsrc_t r1 =
-            make_rsrc(t1 + tile * NS * kTile, (uint32_t)(NS * kTile * 4));
-        const int64_t g = tile * kTile + lane;
-        int n[MT];
-#pragma unroll
-        for (int m = 0; m < MT; ++m) {
-            n[m] = (int)occ[(tile * MT + m) * kTile + lane];
-            occ_lds[m * kTile + lane] = n[m];
-        }
-        int32_t t[CH];
-#pragma unroll
-        for (int i = 0; i < CH; ++i) {
-            if constexpr (!RED) {
-                t[i] = buf_ld_i32(r2, (uint32_t)(((J0 + i) * kTile + lane) * 4), 0);
-            } else {
-                const int j = J0 + i, q = j / MT, l = j % MT;
-                // match {q, l} against the removal multiset {k, s}
-                bool mk = false, ms = false;
-                const bool qm = q == k || q == s;
-                if (q == k) mk = true; else if (q == s) ms = true;
-                bool lm = false;
-                if (l == k && !mk) { mk = true; lm = true; }
-                else if (l == s && !ms) { ms = true; lm = true; }
-                const int shared = (int)qm + (int)lm;
-                if (shared == 2) {
-                    t[i] = g < D ? (int32_t)g : -1;
-                } else if (shared == 1) {
-                    const int a = mk ? s : k, b = qm ? l : q;
-                    t[i] = buf_ld_i32(r1, (uint32_t)(((a * MT + b) * kTile + lane) * 4), 0);
-                } else {
-                    const int r = reduced_rank(MT, k, s, q < l ? q : l, q < l ? l : q);
-                    t[i] = buf_ld_i32(r2, (uint32_t)((r * kTile + lane) * 4), 0);
-                }
-            }
-        }
-        const double2 cg = ldc(g < D ? (int32_t)g : -1);
-        const int nk = occ_lds[k * kTile + lane], ns = occ_lds[s * kTile + lane];
-        const bool valid = k == s ? nk >= 2 : (nk >= 1 && ns >= 1);
-        const double A = valid ? sq[nk] * (k == s ? sq[max(nk - 1, 0)] : sq[ns]) : 0.0;
-        double2 c[CH];
-#pragma unroll
-        for (int i = 0; i < CH; ++i) c[i] = ldc(t[i]);
-        // conj(C_g) * A folded once per row
-        const double xr = cg.x * A, xi = -cg.y * A;
-#pragma unroll
-        for (int i = 0; i < CH; ++i) {
-            const int j = J0 + i, q = j / MT, l = j % MT;
-            // creation amplitudes on m = n - e_k - e_s (rows with A = 0 may go below 0)
-            const int mq = max(n[q] - (q == k) - (q == s), 0);
-            const int ml = max(n[l] - (l == k) - (l == s), 0);
-            const double B = q == l ? sq[mq + 1] * sq[mq + 2] : sq[mq + 1] * sq[ml + 1];
-            const double pr = xr * c[i].x - xi * c[i].y, pi = xr * c[i].y + xi * c[i].x;
-            ar[i] = fma(pr, B, ar[i]);
-            ai[i] = fma(pi, B, ai[i]);
-        }
-    }
-    constexpr int E = NP * NS;
-#pragma unroll
-    for (int i = 0; i < CH; ++i) {
-        const double vr = wave_sum(ar[i]), vi = wave_sum(ai[i]);
-        if (lane == 0) part[(int64_t)wave * E + p * NS + J0 + i] = make_double2(vr, vi);
-    }
-}
-
-template <int MT, typename OccT, bool RED, int... Js>
-__device__ __forceinline__ void rho2_pair(std::integer_sequence<int, Js...>, int k, int s, int p,
-                                          int64_t D, int64_t tiles, int nwaves, int wave,
-                                          int64_t cap, const OccT *__restrict__ occ,
-                                          const int32_t *__restrict__ t1,
-                                          const uint64_t *__restrict__ pmask,
-                                          const int64_t *__restrict__ t2_off,
-                                          const int32_t *__restrict__ t2, const Gather<false> &ldc,
-                                          const double *sq, int *occ_lds,
-                                          double2 *__restrict__ part)
-{
-    (rho2_chunk<MT, OccT, RED, Js * kRhoChunk>(k, s, p, D, tiles, nwaves, wave, cap, occ, t1,
-                                               pmask, t2_off, t2, ldc, sq, occ_lds, part),
-     ...);
-}
-
-// Dynamic LDS: sqrt table (N+3 doubles), then per wavefront an int
-// occupation row [M][64].
-template <int MT, typename OccT, bool RED>
-__global__ __launch_bounds__(256) void k_rho2(int N, int64_t D, int64_t tiles, int nwaves,
-                                               int64_t cap, const OccT *__restrict__ occ,
-                                               const int32_t *__restrict__ t1,
-                                               const uint64_t *__restrict__ pmask,
-                                               const int64_t *__restrict__ t2_off,
-                                               const int32_t *__restrict__ t2,
-                                               const double2 *__restrict__ C,
-                                               double2 *__restrict__ part)
-{
-    extern __shared__ double sq[];
-    fill_sqrt_table(sq, N + 3);
-    int *occ_lds = (int *)(sq + N + 3) + wave_in_block() * MT * kTile;
-    const int wave = blockIdx.x * 4 + wave_in_block();
-    if (wave >= nwaves) return;
-    const Gather<false> ldc(C, D);
-    constexpr int NCH = (MT * MT + kRhoChunk - 1) / kRhoChunk;
-    int p = 0;
-#pragma unroll 1
-    for (int k = 0; k < MT; ++k) {
-#pragma unroll 1
-        for (int s = k; s < MT; ++s, ++p)
-            rho2_pair<MT, OccT, RED>(std::make_integer_sequence<int, NCH>{}, k, s, p, D, tiles,
-                                     nwaves, wave, cap, occ, t1, pmask, t2_off, t2, ldc, sq,
-                                     occ_lds, part);
-    }
-}
-
-// out[e] = sum over waves of part[w][e], in increasing w.
-__global__ void k_rho1_finalize(int E, int nwaves, const double2 *__restrict__ part,
-                                double2 *__restrict__ out)
-{
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= E) return;
-    double sr = 0.0, si = 0.0;
-    for (int w = 0; w < nwaves; ++w) {
-        const double2 v = part[(int64_t)w * E + e];
-        sr += v.x;
-        si += v.y;
-    }
-    out[e] = make_double2(sr, si);
-}
-
-// rho2[k][s][q][l] from the canonical (k <= s) partials.
-__global__ void k_rho2_finalize(int M, int nwaves, const double2 *__restrict__ part,
-                                double2 *__restrict__ out)
-{
-    const int total = M * M * M * M;
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= total) return;
-    const int l = idx % M, q = (idx / M) % M, s = (idx / (M * M)) % M, k = idx / (M * M * M);
-    const int a = k < s ? k : s, b = k < s ? s : k;
-    const int p = a * M - a * (a - 1) / 2 + (b - a);
-    const int E = M * (M + 1) / 2 * M * M;
-    const int e = p * M * M + q * M + l;
-    double sr = 0.0, si = 0.0;
-    for (int w = 0; w < nwaves; ++w) {
-        const double2 v = part[(int64_t)w * E + e];
-        sr += v.x;
-        si += v.y;
-    }
-    out[idx] = make_double2(sr, si);
 }
 
 // ---------------------------------------------------------------------------
@@ -844,6 +546,46 @@ __global__ __launch_bounds__(256) void k_is_hermitian(int M, const double2 *__re
     if (threadIdx.x == 0) flag[0] = ok;
 }
 
+int rho1_generic(int32_t N, int32_t M, const mc_tables *t, const double *C_d, double *rho1_d,
+                 void *ws_d, size_t ws_bytes, mc_stream stream)
+{
+    int st = check_nm(N, M);
+    if (st) return st;
+    st = check_tables(N, M, t, false);
+    if (st) return st;
+    if (!C_d || !rho1_d || !ws_d) return MC_EINVAL;
+    size_t need = 0;
+    mc_workspace_size(N, M, MC_OP_RHO1, &need);
+    if (ws_bytes < need) return MC_ENOMEM;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t D = t->dim;
+    const int nw = rho_waves(t->tiles);
+    const bool big = D * 16 > (int64_t)0xFFFFFFFFu;
+    double2 *part = (double2 *)ws_d;
+    if (occ_width(N) == 1) {
+        if (big)
+            hipLaunchKernelGGL((k_rho1_generic<0, uint8_t, true>), dim3((nw + 3) / 4), dim3(256),
+                               0, s, M, D, t->tiles, nw, (const uint8_t *)t->occ_d, t->t1_d,
+                               (const double2 *)C_d, part);
+        else
+            hipLaunchKernelGGL((k_rho1_generic<0, uint8_t, false>), dim3((nw + 3) / 4), dim3(256),
+                               0, s, M, D, t->tiles, nw, (const uint8_t *)t->occ_d, t->t1_d,
+                               (const double2 *)C_d, part);
+    } else {
+        if (big)
+            hipLaunchKernelGGL((k_rho1_generic<0, uint16_t, true>), dim3((nw + 3) / 4), dim3(256),
+                               0, s, M, D, t->tiles, nw, (const uint16_t *)t->occ_d, t->t1_d,
+                               (const double2 *)C_d, part);
+        else
+            hipLaunchKernelGGL((k_rho1_generic<0, uint16_t, false>), dim3((nw + 3) / 4),
+                               dim3(256), 0, s, M, D, t->tiles, nw, (const uint16_t *)t->occ_d,
+                               t->t1_d, (const double2 *)C_d, part);
+    }
+    // element e = k M + l, summed over waves by the fixed tree
+    hipLaunchKernelGGL(k_gram_sum, dim3(M * M), dim3(256), 0, s, nw, part, (double2 *)rho1_d);
+    return launch_status();
+}
+
 }  // namespace mc
 
 using namespace mc;
@@ -955,9 +697,15 @@ int mc_workspace_size(int32_t N, int32_t M, int32_t op, size_t *bytes)
         *bytes = (size_t)(paper > split ? paper : split);
         return MC_OK;
     }
-    case MC_OP_RHO1: *bytes = (size_t)rho_waves(tiles) * M * M * 16; return MC_OK;
-    case MC_OP_RHO2: *bytes = (size_t)rho_waves(tiles) * P * M * M * 16; return MC_OK;
+    case MC_OP_RHO1:
+        *bytes = M > 8 ? (size_t)rho_waves(tiles) * M * M * 16 : gram_table_workspace(N, M, 1);
+        return *bytes ? MC_OK : MC_ERANGE;
+    case MC_OP_RHO2:
+        *bytes = M > 8 ? 16 : gram_table_workspace(N, M, 2);
+        return *bytes ? MC_OK : MC_ERANGE;
     case MC_OP_DOT: *bytes = (size_t)(MC_DOT_BLOCKS + 1) * 16; return MC_OK;
+    case MC_OP_RHO1_DIRECT: *bytes = gram_workspace(N, M, 1); return *bytes ? MC_OK : MC_ERANGE;
+    case MC_OP_RHO2_DIRECT: *bytes = gram_workspace(N, M, 2); return *bytes ? MC_OK : MC_ERANGE;
     default: return MC_EINVAL;
     }
 }
@@ -1186,91 +934,6 @@ int mc_is_hermitian(int32_t M, const double *h_d, const double *g_d, int32_t *fl
     if (M < 1 || M > MC_MAX_M || !h_d || !g_d || !flag_d) return MC_EINVAL;
     hipLaunchKernelGGL(k_is_hermitian, dim3(1), dim3(256), 0, (hipStream_t)stream, M,
                        (const double2 *)h_d, (const double2 *)g_d, flag_d);
-    return launch_status();
-}
-
-int mc_rho1(int32_t N, int32_t M, const mc_tables *t, const double *C_d, double *rho1_d,
-            void *ws_d, size_t ws_bytes, mc_stream stream)
-{
-    int st = check_nm(N, M);
-    if (st) return st;
-    st = check_tables(N, M, t, false);
-    if (st) return st;
-    if (!C_d || !rho1_d || !ws_d) return MC_EINVAL;
-    size_t need = 0;
-    mc_workspace_size(N, M, MC_OP_RHO1, &need);
-    if (ws_bytes < need) return MC_ENOMEM;
-    hipStream_t s = (hipStream_t)stream;
-    const int64_t D = t->dim;
-    const int nw = rho_waves(t->tiles);
-    const bool big = D * 16 > (int64_t)0xFFFFFFFFu;
-    double2 *part = (double2 *)ws_d;
-    bool launched = false;
-#define MC_RHO1_LAUNCH(OT, BIG)                                                                 \
-    MC_DISPATCH_M(M, if constexpr (MT > 0 && (MT <= 5 || sizeof(OT) == 1)) {                      \
-        hipLaunchKernelGGL((k_rho1<MT, OT, BIG>), dim3((nw + 3) / 4), dim3(256), sqb, s, N, D,    \
-                           t->tiles, nw, (const OT *)t->occ_d, t->t1_d, (const double2 *)C_d,     \
-                           part);                                                                \
-        launched = true;                                                                         \
-    } else if constexpr (MT == 0) {                                                              \
-        hipLaunchKernelGGL((k_rho1_generic<0, OT, BIG>), dim3((nw + 3) / 4), dim3(256), 0, s, M,  \
-                           D, t->tiles, nw, (const OT *)t->occ_d, t->t1_d, (const double2 *)C_d,  \
-                           part);                                                                \
-        launched = true;                                                                         \
-    })
-    const size_t sqb = (size_t)(N + 3) * 8;
-    if (sqb > 65536) return MC_EINVAL;
-    if (occ_width(N) == 1) {
-        if (big) { MC_RHO1_LAUNCH(uint8_t, true); } else { MC_RHO1_LAUNCH(uint8_t, false); }
-    } else {
-        if (big) { MC_RHO1_LAUNCH(uint16_t, true); } else { MC_RHO1_LAUNCH(uint16_t, false); }
-    }
-#undef MC_RHO1_LAUNCH
-    if (!launched) return MC_EINVAL;
-    const int E = M * M;
-    hipLaunchKernelGGL(k_rho1_finalize, dim3((E + 255) / 256), dim3(256), 0, s, E, nw, part,
-                       (double2 *)rho1_d);
-    return launch_status();
-}
-
-int mc_rho2(int32_t N, int32_t M, const mc_tables *t, const double *C_d, double *rho2_d,
-            void *ws_d, size_t ws_bytes, mc_stream stream)
-{
-    int st = check_nm(N, M);
-    if (st) return st;
-    st = check_tables(N, M, t, true);
-    if (st) return st;
-    if (!C_d || !rho2_d || !ws_d) return MC_EINVAL;
-    const bool red = t->form == MC_FORM_REDUCED;
-    size_t need = 0;
-    mc_workspace_size(N, M, MC_OP_RHO2, &need);
-    if (ws_bytes < need) return MC_ENOMEM;
-    hipStream_t s = (hipStream_t)stream;
-    const int64_t D = t->dim;
-    const int nw = rho_waves(t->tiles);
-    const bool big = D * 16 > (int64_t)0xFFFFFFFFu;
-    double2 *part = (double2 *)ws_d;
-    bool launched = false;
-#define MC_RHO2_LAUNCH(OT, RED)                                                                 \
-    MC_DISPATCH_M(M, if constexpr (MT > 0 && (MT <= 5 || sizeof(OT) == 1)) {                      \
-        hipLaunchKernelGGL((k_rho2<MT, OT, RED>), dim3((nw + 3) / 4), dim3(256), lds, s, N, D,     \
-                           t->tiles, nw, t->t2_entries, (const OT *)t->occ_d, t->t1_d,            \
-                           t->pmask_d, t->t2_off_d, t->t2_d, (const double2 *)C_d, part);        \
-        launched = true;                                                                         \
-    })
-    const size_t lds = (size_t)(N + 3) * 8 + (size_t)4 * M * kTile * 4;
-    // the double-jump map cannot exist for D >= 2^28 (it would exceed HBM)
-    if (M > 8 || lds > 65536 || big) return MC_EINVAL;
-    if (occ_width(N) == 1) {
-        if (red) { MC_RHO2_LAUNCH(uint8_t, true); } else { MC_RHO2_LAUNCH(uint8_t, false); }
-    } else {
-        if (red) { MC_RHO2_LAUNCH(uint16_t, true); } else { MC_RHO2_LAUNCH(uint16_t, false); }
-    }
-#undef MC_RHO2_LAUNCH
-    if (!launched) return MC_EINVAL;
-    const int total = M * M * M * M;
-    hipLaunchKernelGGL(k_rho2_finalize, dim3((total + 255) / 256), dim3(256), 0, s, M, nw, part,
-                       (double2 *)rho2_d);
     return launch_status();
 }
 

@@ -237,7 +237,8 @@ def test_direct_energy_gradients(mc):
 @pytest.mark.parametrize("N,M", [(4, 3), (10, 5), (6, 6), (5, 8)])
 def test_direct_adjoint_matches_oracle(mc, oracle_native, N, M):
     """Table-free H^dagger C with no symmetry of h or g: the oracle's H with
-    h -> h^dagger, g_ksql -> conj(g_lqsk); equal to the reduced-table adjoint."""
+    h -> h^dagger, g_ksql -> conj(g_lqsk); equal to the adjoint on reduced
+    tables that chain single jumps (the same terms in the same order)."""
     rng = np.random.default_rng(N * 10 + M + 1)
     h = rng.standard_normal((M, M)) + 1j * rng.standard_normal((M, M))
     g = rng.standard_normal((M,) * 4) + 1j * rng.standard_normal((M,) * 4)
@@ -246,8 +247,14 @@ def test_direct_adjoint_matches_oracle(mc, oracle_native, N, M):
     adj = mc.apply_H_adjoint(dev(h), dev(g), dev(C), mc.DirectSpace(N, M))
     ref = oracle_native.apply_h(N, M, h.conj().T, np.transpose(g, (3, 2, 1, 0)).conj(), C)
     assert rel_inf(adj.cpu().numpy(), ref) <= TOL
-    tab = mc.apply_H_adjoint(dev(h), dev(g), dev(C), mc.build_tables(N, M, form="reduced"))
-    assert torch.equal(adj, tab)
+    tab = mc.apply_H_adjoint(dev(h), dev(g), dev(C),
+                             mc.build_tables(N, M, form="reduced", double_jumps=False))
+    if M < 8:
+        assert torch.equal(adj, tab)
+    else:   # M = 8: the two bodies split the slot stream differently
+        assert rel_inf(adj.cpu().numpy(), tab.cpu().numpy()) <= 1e-14
+    mapped = mc.apply_H_adjoint(dev(h), dev(g), dev(C), mc.build_tables(N, M, form="reduced"))
+    assert rel_inf(mapped.cpu().numpy(), ref) <= TOL
 
 
 def test_direct_density_matrices_reject_bad_sizes(mc):

@@ -113,3 +113,77 @@ def test_zdotc(mc):
         got = mc.zdotc(dev(x), dev(y)).item()
         ref = np.vdot(x, y)
         assert abs(got - ref) <= 1e-13 * np.sum(np.abs(x) * np.abs(y))
+
+
+KINDS = {  # space kind: (form, double-jump map); None = table-free
+    "paper_map": ("paper", True),
+    "reduced_map": ("reduced", True),
+    "paper_chained": ("paper", False),
+    "reduced_chained": ("reduced", False),
+    "direct": (None, None),
+}
+
+
+def make_space(mc, kind, N, M):
+    form, has_map = KINDS[kind]
+    if form is None:
+        return mc.DirectSpace(N, M)
+    return mc.build_tables(N, M, form=form, double_jumps=has_map)
+
+
+# one particle (rho2 = 0), two (a single N-2 configuration), one orbital,
+# ragged tiles, M = 8, more than 255 particles
+@pytest.mark.parametrize("N,M,seed", [(1, 4, 0), (2, 3, 1), (2, 1, 2), (5, 1, 3), (4, 6, 4),
+                                      (9, 8, 5), (13, 5, 6), (300, 2, 7), (33, 3, 8), (8, 7, 9)])
+@pytest.mark.parametrize("kind", list(KINDS))
+def test_rho_every_space_kind(mc, oracle_native, kind, N, M, seed):
+    """Eqs. rho1, rho2 through each source of targets (maps of either form,
+    chained single jumps, closed form) against the oracle."""
+    C, _, _ = W.random_instance(N, M, seed)
+    sp = make_space(mc, kind, N, M)
+    Cd = dev(C)
+    r1 = mc.rho1(Cd, sp).cpu().numpy()
+    r2 = mc.rho2(Cd, sp).cpu().numpy()
+    assert rel_inf(r1, oracle_native.rho1(N, M, C)) <= TOL
+    ref2 = oracle_native.rho2(N, M, C)
+    if N < 2:
+        assert not np.any(r2) and not np.any(ref2)
+    assert rel_inf(r2, ref2) <= TOL
+
+
+@pytest.mark.parametrize("kind", list(KINDS))
+def test_rho_symmetries_exact(mc, kind):
+    """rho_lk = conj(rho_kl); rho_ksql = rho_skql = rho_kslq = conj(rho_qlks),
+    bit for bit; diagonal elements real."""
+    N, M = 11, 6
+    C, _, _ = W.random_instance(N, M, 31)
+    sp = make_space(mc, kind, N, M)
+    Cd = dev(C)
+    r1, r2 = mc.rho1(Cd, sp), mc.rho2(Cd, sp)
+    assert torch.equal(r1, r1.T.conj().resolve_conj())
+    assert torch.equal(r2, r2.permute(1, 0, 2, 3).contiguous())
+    assert torch.equal(r2, r2.permute(0, 1, 3, 2).contiguous())
+    assert torch.equal(r2, r2.permute(2, 3, 0, 1).conj().resolve_conj().contiguous())
+    assert not torch.any(torch.diagonal(r1).imag)
+
+
+@pytest.mark.parametrize("kind", ["reduced_map", "direct"])
+def test_rho_headline_size_invariants(mc, kind):
+    """N = 200, M = 5 (dim 70,058,751), seed 2: tr rho1 = N, sum_s rho_kssl =
+    (N-1) rho_kl, and E = sum h rho1 + 1/2 sum g rho2 equals <C|HC> from the
+    apply on the same space (Sec. II; the apply is checked against the oracle
+    at this size elsewhere)."""
+    N, M = 200, 5
+    C, h, g = W.random_instance(N, M, 2)
+    sp = make_space(mc, kind, N, M)
+    Cd, hd, gd = dev(C), dev(h), dev(g)
+    r1, r2 = mc.rho1(Cd, sp), mc.rho2(Cd, sp)
+    HC = mc.apply_H(hd, gd, Cd, sp)
+    E = mc.zdotc(Cd, HC).item()
+    E2 = (torch.sum(hd * r1) + 0.5 * torch.sum(gd * r2)).item()
+    r1n, r2n = r1.cpu().numpy(), r2.cpu().numpy()
+    assert abs(np.trace(r1n) - N) <= 1e-12 * N
+    assert rel_inf(np.einsum("kssl->kl", r2n), (N - 1) * r1n) <= 1e-12
+    assert abs(E - E2) <= 1e-12 * abs(E)
+    del sp, HC
+    torch.cuda.empty_cache()

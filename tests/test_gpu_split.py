@@ -105,13 +105,14 @@ def test_rho2_agrees_across_forms(mc):
     assert rel_inf(b, a) <= TOL
 
 
-def test_rho2_needs_a_map(mc):
-    tab = mc.build_tables(6, 4, form="reduced", double_jumps=False)
-    C = torch.ones(tab.dim, dtype=torch.complex128, device="cuda")
-    with pytest.raises(mc.MCError):
-        mc.rho2(C, tab)
-    # rho1 reads only the single-jump map
-    assert torch.isfinite(mc.rho1(C, tab).real).all()
+def test_rho2_without_a_map_chains_single_jumps(mc, oracle_native):
+    """Tables without a double-jump map: rho2's targets m + e_q + e_l are two
+    chained single jumps out of orbital 0 (Sec. IV)."""
+    N, M = 6, 4
+    tab = mc.build_tables(N, M, form="reduced", double_jumps=False)
+    C, _, _ = W.random_instance(N, M, 5)
+    r2 = mc.rho2(torch.from_numpy(C).cuda(), tab).cpu().numpy()
+    assert rel_inf(r2, oracle_native.rho2(N, M, C)) <= TOL
 
 
 def test_split_rejects_more_than_eight_orbitals(mc):

@@ -73,11 +73,14 @@ def random_symmetric_g(rng: np.random.Generator, M: int) -> np.ndarray:
     A complex Gaussian tensor G is averaged over the order-8 group generated
     by  k<->s,  q<->l  and  (k,s,q,l) -> conj(q,l,k,s), so that
     g_ksql = g_skql = g_kslq = conj(g_qlks); with these the Hamiltonian is
-    Hermitian.
+    Hermitian.  The average is taken one generator at a time (three
+    two-term means), so every symmetry holds bit for bit: a two-term sum is
+    the same in either order, a four- or eight-term sum in another order
+    need not be.
     """
     G = rng.standard_normal((M,) * 4) + 1j * rng.standard_normal((M,) * 4)
-    S = (G + G.transpose(1, 0, 2, 3) + G.transpose(0, 1, 3, 2)
-         + G.transpose(1, 0, 3, 2)) / 4.0
+    S = (G + G.transpose(1, 0, 2, 3)) / 2.0
+    S = (S + S.transpose(0, 1, 3, 2)) / 2.0
     g = (S + S.transpose(2, 3, 0, 1).conj()) / 2.0
     return np.ascontiguousarray(g)
 
