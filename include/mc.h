@@ -290,6 +290,21 @@ int mc_apply_H_direct(int32_t N, int32_t M, const double *h_d, const double *g_d
                       const double *C_d, double *HC_d, void *ws_d, size_t ws_bytes,
                       mc_stream stream);
 
+/* mc_apply_H_direct without a workspace argument, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the call itself allocates nothing.  The staged constants
+ * go to a device array owned by the library, MC_NOALLOC_SCRATCH_BYTES bytes,
+ * one per GPU, held until the process ends; its address is looked up once per
+ * device, on the first call with that device current.  Every call on a GPU
+ * shares that GPU's array and the last call's constants stay in it: calls on
+ * one stream are ordered, calls that overlap on one GPU (other streams, other
+ * host threads) race.  MC_ENOMEM if the constants of (N, M) exceed the array
+ * (never for M <= 8); other arguments, limits and errors as
+ * mc_apply_H_direct, whose kernels it runs. */
+#define MC_NOALLOC_SCRATCH_BYTES 65536
+int mc_apply_H_direct_noalloc(int32_t N, int32_t M, const double *h_d, const double *g_d,
+                              const double *C_d, double *HC_d, mc_stream stream);
+
 /* HC_d = H^dagger . C_d with no table (h -> h^dagger, g_ksql -> conj(g_lqsk)),
  * the table-free counterpart of mc_apply_H_adjoint; arguments, limits and
  * errors as mc_apply_H_direct. */

@@ -110,6 +110,7 @@ SIGNATURES = {
     "mc_apply_H_sparse": (ctypes.c_int, [c_i32, c_i32, c_p, c_p, ctypes.POINTER(CTables), c_p, c_p,
                                          c_p, c_sz, c_p]),
     "mc_apply_H_direct": (ctypes.c_int, [c_i32, c_i32, c_p, c_p, c_p, c_p, c_p, c_sz, c_p]),
+    "mc_apply_H_direct_noalloc": (ctypes.c_int, [c_i32, c_i32, c_p, c_p, c_p, c_p, c_p]),
     "mc_rho1_direct": (ctypes.c_int, [c_i32, c_i32, c_p, c_p, c_p, c_sz, c_p]),
     "mc_rho2_direct": (ctypes.c_int, [c_i32, c_i32, c_p, c_p, c_p, c_sz, c_p]),
     "mc_tridiag_expv": (ctypes.c_int, [c_i32, c_p, c_p, ctypes.c_double, c_p]),

@@ -9,6 +9,7 @@
 // from an empty orbital) and padding rows load through a range-checked
 // buffer resource and read as zero, so the inner loops have no branches on
 // row validity; only the tile-uniform pair mask branches.
+#include <mutex>
 #include <utility>
 
 #include "mc_apply.h"
@@ -877,6 +878,36 @@ int mc_apply_H_sparse(int32_t N, int32_t M, const double *h_d, const double *g_d
     return launch_status();
 }
 
+// Scratch of mc_apply_H_direct_noalloc: the staged constants of the apply
+// live in this file-scope device array (one copy per GPU, held until the
+// process ends) instead of a caller workspace.  Host code never passes the
+// array's name to a kernel: its device address is looked up once per device
+// (with that device current) and kept per device.
+static __device__ __align__(256) unsigned char scratch[MC_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+static int noalloc_scratch(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return set_hip_error(e);
+    if (dev < 0 || dev >= kMaxDevices) return MC_EINVAL;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return set_hip_error(e != hipSuccess ? e : hipErrorUnknown);
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return MC_OK;
+}
+
 static int apply_direct_common(int32_t N, int32_t M, const double *h_d, const double *g_d,
                                const double *C_d, double *HC_d, void *ws_d, size_t ws_bytes,
                                int adjoint, mc_stream stream)
@@ -919,6 +950,20 @@ int mc_apply_H_direct(int32_t N, int32_t M, const double *h_d, const double *g_d
                       mc_stream stream)
 {
     return apply_direct_common(N, M, h_d, g_d, C_d, HC_d, ws_d, ws_bytes, 0, stream);
+}
+
+int mc_apply_H_direct_noalloc(int32_t N, int32_t M, const double *h_d, const double *g_d,
+                              const double *C_d, double *HC_d, mc_stream stream)
+{
+    size_t need = 0;
+    int st = mc_workspace_size(N, M, MC_OP_APPLY, &need);
+    if (st) return st;
+    if (need > (size_t)MC_NOALLOC_SCRATCH_BYTES) return MC_ENOMEM;
+    void *ws = nullptr;
+    st = noalloc_scratch(&ws);
+    if (st) return st;
+    return apply_direct_common(N, M, h_d, g_d, C_d, HC_d, ws, MC_NOALLOC_SCRATCH_BYTES, 0,
+                               stream);
 }
 
 int mc_apply_H_direct_adjoint(int32_t N, int32_t M, const double *h_d, const double *g_d,
