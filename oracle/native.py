@@ -37,8 +37,12 @@ def _load():
     global _lib
     with _lock:
         if _lib is None:
-            build(force=False)
-            lib = ctypes.CDLL(_LIB)
+            # MC_ORACLE_LIBRARY: another build of mc_oracle.c (the sanitizer build)
+            path = os.environ.get("MC_ORACLE_LIBRARY")
+            if not path:
+                build(force=False)
+                path = _LIB
+            lib = ctypes.CDLL(path)
             i32, i64, p = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
             lib.orc_nc.argtypes = [i64, i64]
             lib.orc_nc.restype = i64

@@ -171,10 +171,12 @@ def load():
     with _lock:
         if _lib is not None:
             return _lib
-        if not os.path.exists(LIB_PATH):
+        # MC_LIBRARY: another build of the same sources (the sanitizer build)
+        path = os.environ.get("MC_LIBRARY") or LIB_PATH
+        if not os.path.exists(path):
             raise RuntimeError(
-                f"{LIB_PATH} is not built; run `python -m paper_2005_13679_amd.build`")
-        lib = ctypes.CDLL(LIB_PATH)
+                f"{path} is not built; run `python -m paper_2005_13679_amd.build`")
+        lib = ctypes.CDLL(path)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(lib, name)
             fn.restype = res

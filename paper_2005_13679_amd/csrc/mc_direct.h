@@ -56,13 +56,6 @@ __device__ __forceinline__ double direct_g(int m, double x)
     return rint(direct_prod(m, x) * (1.0 / direct_fact(m + 1)));
 }
 
-// Change of S_m when particles leave R1, R2 and enter A1, A2 (-1: none).
-__host__ __device__ constexpr int prefix_delta(int m, int R1, int R2, int A1, int A2)
-{
-    return (A1 >= 0 && A1 <= m) + (A2 >= 0 && A2 <= m) - (R1 >= 0 && R1 <= m) -
-           (R2 >= 0 && R2 <= m);
-}
-
 // Prefix sums S_0..S_{M-1} of row `row` (0 <= row < D) of the space of N
 // particles: greedily from J = D - 1 - row, S_m = the largest s <= S_{m+1}
 // with G_m(s) <= what is left of J, m = M-2 .. 1, then S_0 = the rest.

@@ -327,7 +327,9 @@ __device__ __forceinline__ void split_pairs_chain(std::integer_sequence<int, Ps.
 // U = M(M-1) + sum_p nd(p) slots with a compile-time layout, processed in
 // batches of MC_FLAT_BATCH slots; the next batch's index loads are issued
 // while the current batch's gathers are in flight.  Same arithmetic, in the
-// same order, as the per-pair path.
+// same order, as the per-pair path.  The build default walks the same slots
+// in class-major order instead (below), which gathers fewer coefficients and
+// groups the terms differently (results agree to rounding).
 // ---------------------------------------------------------------------------
 #ifndef MC_FLAT_BATCH
 #define MC_FLAT_BATCH 16
@@ -495,6 +497,328 @@ __device__ __forceinline__ void flat_batches(int32_t (&cur)[FlatTile<MT>::SB],
     }
 }
 
+// ---------------------------------------------------------------------------
+// Class-major stream: fewer coefficient gathers per tile.
+//
+// Consecutive rows of a run (indices that differ by one particle moved
+// between orbitals 0 and 1) share the prefix sums S_1 .. S_{M-1} (mc_direct.h
+// has the closed form of the index), so a jump that changes S_m by Delta_m
+// reaches index  g - Delta_0 + K,  where K depends only on the run and on
+// (Delta_1 .. Delta_{M-2}).  Jumps with equal (Delta_1 .. Delta_{M-2}) form a
+// class: slot U needs at lane i the coefficient its class's anchor reads at
+// lane i + s, s = Delta_0(anchor) - Delta_0(U), whenever both lanes hold rows
+// of one run.  Each class gathers once (the anchor) and its other slots take
+// the anchor's value from lane i + s (DPP wave shifts), re-gathering only on
+// the lanes where the shifted anchor index differs from their own (run and
+// tile edges): equal indices give equal values, so the result never depends
+// on the run structure, only the gather count does.  The row's own
+// coefficient anchors the class of jumps within orbitals {0, 1}.  M = 5:
+// 130 slots, 54 anchors.
+// ---------------------------------------------------------------------------
+
+// Change of S_m when particles leave R1, R2 and enter A1, A2 (-1: none).
+__host__ __device__ constexpr int prefix_delta(int m, int R1, int R2, int A1, int A2)
+{
+    return (A1 >= 0 && A1 <= m) + (A2 >= 0 && A2 <= m) - (R1 >= 0 && R1 <= m) -
+           (R2 >= 0 && R2 <= m);
+}
+
+// Removed (R1, R2) and created (A1, A2) orbitals of slot U of the flat
+// stream (-1: none); U = -1 is the row itself.
+template <int MT>
+__host__ __device__ constexpr void flat_jump(int U, int &R1, int &R2, int &A1, int &A2)
+{
+    R1 = R2 = A1 = A2 = -1;
+    if (U < 0) return;
+    constexpr int NSING = MT * (MT - 1);
+    if (U < NSING) {
+        const int a = U / (MT - 1), bb = U % (MT - 1);
+        R1 = a;
+        A1 = bb + (bb >= a);
+        return;
+    }
+    const int e = U - NSING, P = flat_pair(MT, e), r = flat_slot(MT, e);
+    R1 = pair_k(MT, P);
+    R2 = pair_s(MT, P);
+    A1 = reduced_ql(MT, R1, R2, r, 0);
+    A2 = reduced_ql(MT, R1, R2, r, 1);
+}
+
+template <int MT>
+__host__ __device__ constexpr int flat_delta(int U, int m)
+{
+    int R1 = 0, R2 = 0, A1 = 0, A2 = 0;
+    flat_jump<MT>(U, R1, R2, A1, A2);
+    return prefix_delta(m, R1, R2, A1, A2);
+}
+
+#ifndef MC_CLASS_STREAM
+#define MC_CLASS_STREAM 1
+#endif
+#ifndef MC_CLASS_BATCH
+#define MC_CLASS_BATCH 16
+#endif
+
+// The stream in class-major order: position i holds flat slot slot[i] (-1:
+// the row itself), whose value is the anchor at position anc[i] read from
+// lane + sh[i]; batches of whole classes of at most MC_CLASS_BATCH positions.
+template <int MT>
+struct ClassPlan {
+    static constexpr int U = FlatTile<MT>::U;
+    static constexpr int NP = U + 1;
+    int slot[NP] = {};
+    int anc[NP] = {};
+    int sh[NP] = {};
+    int nb = 0;
+    int bstart[NP + 1] = {};
+    int anchors = 0;
+
+    constexpr ClassPlan()
+    {
+        // Delta_0 and the class key (Delta_1 .. Delta_{M-2}, base 5) of each slot
+        int d0[NP] = {}, key[NP] = {};
+        for (int v = -1; v < U; ++v) {
+            d0[v + 1] = flat_delta<MT>(v, 0);
+            int k = 0;
+            for (int m = MT - 2; m >= 1; --m) k = 5 * k + flat_delta<MT>(v, m) + 2;
+            key[v + 1] = k;
+        }
+        bool used[NP] = {};
+        int pos = 0;
+        for (int a = -1; a < U; ++a) {
+            if (used[a + 1]) continue;
+            // a opens a class: it and every later slot of its class
+            const int first = pos;
+            for (int v = a; v < U; ++v) {
+                if (used[v + 1] || key[v + 1] != key[a + 1]) continue;
+                used[v + 1] = true;
+                slot[pos] = v;
+                anc[pos] = first;
+                sh[pos] = d0[a + 1] - d0[v + 1];
+                ++pos;
+            }
+            if (a >= 0) ++anchors;
+        }
+        // greedy batches of whole classes
+        int start = 0;
+        nb = 0;
+        bstart[0] = 0;
+        while (start < NP) {
+            int end = start;
+            while (end < NP) {
+                int cend = end + 1;
+                while (cend < NP && anc[cend] == anc[end]) ++cend;
+                if (end > start && cend - start > MC_CLASS_BATCH) break;
+                end = cend;
+            }
+            bstart[++nb] = end;
+            start = end;
+        }
+    }
+};
+
+template <int MT>
+constexpr ClassPlan<MT> kClassPlan{};
+
+
+// x moved s lanes: lane i receives lane i + s (s > 0: wave_shl, s < 0:
+// wave_shr, one lane per step); lanes with no source get `fill`.
+template <int S>
+__device__ __forceinline__ int32_t lane_shift_i32(int32_t x, int32_t fill)
+{
+    if constexpr (S == 0) return x;
+    else if constexpr (S > 0)
+        return lane_shift_i32<S - 1>(__builtin_amdgcn_update_dpp(fill, x, 0x130, 0xF, 0xF, false),
+                                     fill);
+    else
+        return lane_shift_i32<S + 1>(__builtin_amdgcn_update_dpp(fill, x, 0x138, 0xF, 0xF, false),
+                                     fill);
+}
+
+template <int S>
+__device__ __forceinline__ double2 lane_shift_c128(double2 v)
+{
+    int32_t w[4];
+    __builtin_memcpy(w, &v, 16);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[k] = lane_shift_i32<S>(w[k], 0);
+    double2 r;
+    __builtin_memcpy(&r, w, 16);
+    return r;
+}
+
+// Arithmetic of one slot in the class-major order: a single jump adds
+// sqrt(n_a (n_b+1)) [HS_ab + sum_c n_c GS_abc] C, a true double jump
+// A_KS B_ql GD C (A folded per slot, as the slots of a pair are no longer
+// adjacent).
+template <int MT, int U>
+__device__ __forceinline__ void class_fma(const double2 &c, const RowSq<MT> &R,
+                                          const double (&x)[MT], const double2 *__restrict__ HS,
+                                          const double2 *__restrict__ GS,
+                                          const double2 *__restrict__ GD, double &ar, double &ai)
+{
+    constexpr int NSING = FlatTile<MT>::NSING;
+    if constexpr (U < 0) {
+        return;   // the row itself: its term is added before the stream
+    } else if constexpr (U < NSING) {
+        constexpr int a = U / (MT - 1), bb = U % (MT - 1), b = bb + (bb >= a), j = a * MT + b;
+        double er = HS[j].x, ei = HS[j].y;
+#pragma unroll
+        for (int k = 0; k < MT; ++k) {
+            er = fma(GS[j * MT + k].x, x[k], er);
+            ei = fma(GS[j * MT + k].y, x[k], ei);
+        }
+        const double f = R.template root<0>(a) * R.template root<1>(b);
+        er *= f;
+        ei *= f;
+        ar = fma(er, c.x, ar);
+        ar = fma(-ei, c.y, ar);
+        ai = fma(er, c.y, ai);
+        ai = fma(ei, c.x, ai);
+    } else {
+        constexpr int e = U - NSING;
+        constexpr int P = flat_pair(MT, e), r = flat_slot(MT, e);
+        constexpr int K = pair_k(MT, P), S = pair_s(MT, P);
+        constexpr int q = reduced_ql(MT, K, S, r, 0), l = reduced_ql(MT, K, S, r, 1);
+        const double Bf = q == l ? R.template root<1>(q) * R.template root<2>(q)
+                                 : R.template root<1>(q) * R.template root<1>(l);
+        const double A = R.template root<0>(K) *
+                         (K == S ? R.template root<-1>(K) : R.template root<0>(S));
+        const double w = A * Bf;
+        const double cr = c.x * w, ci = c.y * w;
+        const double2 Gv = GD[e];
+        ar = fma(Gv.x, cr, ar);
+        ar = fma(-Gv.y, ci, ar);
+        ai = fma(Gv.x, ci, ai);
+        ai = fma(Gv.y, cr, ai);
+    }
+}
+
+// Batch B of the class-major stream (positions [I0, I1)): `tix` holds the
+// batch's target indices (from the source: table loads or closed form).
+// Anchor gathers and the members' edge re-gathers are issued together, then
+// the shifts, then the arithmetic.
+template <int MT, bool BIGC, int B, int... Is>
+__device__ __forceinline__ void class_batch(std::integer_sequence<int, Is...>,
+                                            const int32_t (&tix)[MC_CLASS_BATCH], int32_t own_t,
+                                            double2 own_c, const RowSq<MT> &R,
+                                            const double (&x)[MT], const double2 *__restrict__ HS,
+                                            const double2 *__restrict__ GS,
+                                            const double2 *__restrict__ GD,
+                                            const Gather<BIGC> &ldc, double &ar, double &ai)
+{
+    constexpr ClassPlan<MT> cp = kClassPlan<MT>;
+    constexpr int I0 = cp.bstart[B], I1 = cp.bstart[B + 1];
+    double2 v[MC_CLASS_BATCH];
+    // anchors: gather (the row itself: its own coefficient)
+    (
+        [&] {
+            constexpr int i = I0 + Is;
+            if constexpr (i < I1 && cp.anc[i] == i) {
+                if constexpr (cp.slot[i] < 0) v[Is] = own_c;
+                else v[Is] = ldc(tix[Is]);
+            }
+        }(),
+        ...);
+    // members: the anchor's index and value from lane + s (DPP wave shifts);
+    // a re-gather on the lanes where that index differs from the member's own
+    bool need[MC_CLASS_BATCH];
+    (
+        [&] {
+            constexpr int i = I0 + Is;
+            if constexpr (i < I1 && cp.anc[i] != i) {
+                constexpr int ai_ = cp.anc[i] - I0;
+                const int32_t at =
+                    lane_shift_i32<cp.sh[i]>(cp.slot[cp.anc[i]] < 0 ? own_t : tix[ai_], -2);
+                need[Is] = at != tix[Is];
+                v[Is] = ldc(need[Is] ? tix[Is] : -1);
+            }
+        }(),
+        ...);
+    (
+        [&] {
+            constexpr int i = I0 + Is;
+            if constexpr (i < I1 && cp.anc[i] != i) {
+                const double2 s = lane_shift_c128<cp.sh[i]>(v[cp.anc[i] - I0]);
+                if (!need[Is]) v[Is] = s;
+            }
+        }(),
+        ...);
+    (
+        [&] {
+            constexpr int i = I0 + Is;
+            if constexpr (i < I1) class_fma<MT, cp.slot[i]>(v[Is], R, x, HS, GS, GD, ar, ai);
+        }(),
+        ...);
+}
+
+// Target index of class-major position i from the source (the row itself
+// needs none).
+template <int MT, int B, class Src, int... Is>
+__device__ __forceinline__ void class_targets(std::integer_sequence<int, Is...>, const Src &src,
+                                              int32_t (&tix)[MC_CLASS_BATCH])
+{
+    constexpr ClassPlan<MT> cp = kClassPlan<MT>;
+    constexpr int I0 = cp.bstart[B], I1 = cp.bstart[B + 1];
+    (
+        [&] {
+            constexpr int i = I0 + Is;
+            if constexpr (i < I1 && cp.slot[i] >= 0) tix[Is] = src.template target<cp.slot[i]>();
+        }(),
+        ...);
+}
+
+// The whole stream: batch B's block issues batch B+1's targets (table loads
+// in flight during B's gathers), then B's gathers and arithmetic.
+template <int MT, bool BIGC, int B, class Src>
+__device__ __forceinline__ void class_batches(int32_t (&cur)[MC_CLASS_BATCH],
+                                              int32_t (&nxt)[MC_CLASS_BATCH], const Src &src,
+                                              int32_t own_t, double2 own_c, const RowSq<MT> &R,
+                                              const double (&x)[MT],
+                                              const double2 *__restrict__ HS,
+                                              const double2 *__restrict__ GS,
+                                              const double2 *__restrict__ GD,
+                                              const Gather<BIGC> &ldc, double &ar, double &ai)
+{
+    constexpr int NB = kClassPlan<MT>.nb;
+    if constexpr (B < NB) {
+        // each batch in a basic block of its own (see opaque_true)
+        if (opaque_true()) {
+            if constexpr (B + 1 < NB)
+                class_targets<MT, B + 1>(std::make_integer_sequence<int, MC_CLASS_BATCH>{}, src, nxt);
+            class_batch<MT, BIGC, B>(std::make_integer_sequence<int, MC_CLASS_BATCH>{}, cur, own_t,
+                                     own_c, R, x, HS, GS, GD, ldc, ar, ai);
+        }
+        class_batches<MT, BIGC, B + 1>(nxt, cur, src, own_t, own_c, R, x, HS, GS, GD, ldc, ar, ai);
+    }
+}
+
+template <int MT, bool BIGC, class Src>
+__device__ __forceinline__ void class_stream(const Src &src, int32_t own_t, double2 own_c,
+                                             const RowSq<MT> &R, const double (&x)[MT],
+                                             const double2 *__restrict__ HS,
+                                             const double2 *__restrict__ GS,
+                                             const double2 *__restrict__ GD,
+                                             const Gather<BIGC> &ldc, double &ar, double &ai)
+{
+    int32_t ta[MC_CLASS_BATCH], tb[MC_CLASS_BATCH];
+    class_targets<MT, 0>(std::make_integer_sequence<int, MC_CLASS_BATCH>{}, src, ta);
+    class_batches<MT, BIGC, 0>(ta, tb, src, own_t, own_c, R, x, HS, GS, GD, ldc, ar, ai);
+}
+
+// Targets of a full tile through the tables: the tile's single-jump block
+// and its reduced-map block.
+template <int MT>
+struct MapSlots {
+    __amdgpu_buffer_rsrc_t r1, r2;
+    int lane;
+    template <int U>
+    __device__ __forceinline__ int32_t target() const
+    {
+        return flat_load<MT, U>(r1, r2, lane);
+    }
+};
+
 // One 64-row tile of H.C in the case-split form; MAP: true double jumps from
 // the reduced map, else chained.  `cf` holds the staged constants.
 template <int MT, typename OccT, bool BIGC, bool MAP>
@@ -563,10 +887,15 @@ __device__ __forceinline__ void apply_tile_split(int64_t tile, int64_t D, int64_
         if (full) {
             const __amdgpu_buffer_rsrc_t r2 =
                 make_rsrc(t2r + off0, (uint32_t)(FlatTile<MT>::NDBL * kTile * 4));
+#if MC_CLASS_STREAM
+            const MapSlots<MT> src{r1, r2, lane};
+            class_stream<MT, BIGC>(src, live ? (int32_t)g : -2, cg, R, x, HS, GS, GD, ldc, ar, ai);
+#else
             int32_t ta[FlatTile<MT>::SB], tb[FlatTile<MT>::SB];
             flat_loads<MT, 0>(std::make_integer_sequence<int, FlatTile<MT>::SB>{}, ta, r1, r2, lane);
             double br = 0.0, bi = 0.0;
             flat_batches<MT, BIGC, 0>(ta, tb, r1, r2, lane, n, R, x, HS, GS, GD, ldc, br, bi, ar, ai);
+#endif
             if (live) HC[g] = make_double2(ar, ai);
             return;
         }

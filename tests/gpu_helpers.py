@@ -4,6 +4,9 @@ the relative infinity-norm used as the floating-point bar."""
 import numpy as np
 
 TILE = 64
+# two evaluations of the same sums in different orders (paths that group
+# the terms differently) agree to this relative infinity-norm
+ORDER_TOL = 1e-14
 
 
 def rel_inf(a, b) -> float:

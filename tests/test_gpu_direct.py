@@ -1,14 +1,15 @@
 """GPU H.C with no table (mc_apply_H_direct: occupations and jump targets of
 each row from its index in closed form) vs the oracle, relative
 infinity-norm error <= 1e-12, and against the case-split apply on reduced
-tables, which sums the same terms in the same order."""
+tables, which sums the same terms (in another grouping on tiles that do not
+take the class-major stream)."""
 
 import numpy as np
 import pytest
 import torch
 
 import workloads as W
-from tests.gpu_helpers import rel_inf
+from tests.gpu_helpers import ORDER_TOL, rel_inf
 
 pytestmark = pytest.mark.gpu
 
@@ -31,7 +32,7 @@ def test_direct_matches_oracle_and_split(mc, oracle_native, N, M, seed):
     assert rel_inf(got.cpu().numpy(), oracle_native.apply_h(N, M, h, g, C)) <= TOL
     split = mc.apply_H(dev(h), dev(g), dev(C), mc.build_tables(N, M, form="reduced",
                                                                double_jumps=False))
-    assert torch.equal(got, split)
+    assert rel_inf(got.cpu().numpy(), split.cpu().numpy()) <= ORDER_TOL
 
 
 @pytest.mark.parametrize("N,M", [(4, 3), (10, 5), (6, 6), (5, 8), (3, 2), (9, 7)])
@@ -73,7 +74,7 @@ def test_direct_large_space_sampled_rows(mc, oracle_native):
     assert rel_inf(got, oracle_native.apply_h(N, M, h, g, C, rows)) <= TOL
     tab = mc.build_tables(N, M, form="reduced")
     ref = mc.apply_H(dev(h), dev(g), Cd, tab)
-    assert torch.equal(hc, ref)
+    assert rel_inf(hc.cpu().numpy(), ref.cpu().numpy()) <= ORDER_TOL
     del tab, ref, hc, Cd
     torch.cuda.empty_cache()
 
@@ -128,7 +129,7 @@ def test_direct_sil_step_matches_oracle(mc, oracle_native, N, M, seed, k):
     tab, m2, _ = mc.sil_step(mc.build_tables(N, M, form="reduced"), dev(h), dev(g), dev(C), 0.02, k=k)
     assert m == m_ref == m2
     assert rel_inf(got.cpu().numpy(), ref) <= 1e-11
-    assert torch.equal(got, tab)
+    assert rel_inf(got.cpu().numpy(), tab.cpu().numpy()) <= 1e-12
 
 
 def test_direct_lanczos_lieb_liniger_energies(mc):
@@ -219,8 +220,8 @@ def test_direct_energy_gradients(mc):
         E = mc.energy(Ct, ht, gt, space)
         E.real.backward()
         out.append((E.detach(), Ct.grad, ht.grad, gt.grad))
-    assert torch.equal(out[0][0], out[1][0])
-    assert torch.equal(out[0][1], out[1][1])
+    assert abs(out[0][0].item() - out[1][0].item()) <= ORDER_TOL * abs(out[1][0].item())
+    assert rel_inf(out[0][1].cpu().numpy(), out[1][1].cpu().numpy()) <= ORDER_TOL
     for i in (2, 3):
         assert rel_inf(out[0][i].cpu().numpy(), out[1][i].cpu().numpy()) <= TOL
     rng = np.random.default_rng(72)
@@ -231,7 +232,7 @@ def test_direct_energy_gradients(mc):
         Ct = dev(C).requires_grad_(True)
         mc.energy(Ct, dev(hn), dev(gn), space).real.backward()
         grads.append(Ct.grad)
-    assert torch.equal(grads[0], grads[1])
+    assert rel_inf(grads[0].cpu().numpy(), grads[1].cpu().numpy()) <= ORDER_TOL
 
 
 @pytest.mark.parametrize("N,M", [(4, 3), (10, 5), (6, 6), (5, 8)])
@@ -249,10 +250,7 @@ def test_direct_adjoint_matches_oracle(mc, oracle_native, N, M):
     assert rel_inf(adj.cpu().numpy(), ref) <= TOL
     tab = mc.apply_H_adjoint(dev(h), dev(g), dev(C),
                              mc.build_tables(N, M, form="reduced", double_jumps=False))
-    if M < 8:
-        assert torch.equal(adj, tab)
-    else:   # M = 8: the two bodies split the slot stream differently
-        assert rel_inf(adj.cpu().numpy(), tab.cpu().numpy()) <= 1e-14
+    assert rel_inf(adj.cpu().numpy(), tab.cpu().numpy()) <= ORDER_TOL
     mapped = mc.apply_H_adjoint(dev(h), dev(g), dev(C), mc.build_tables(N, M, form="reduced"))
     assert rel_inf(mapped.cpu().numpy(), ref) <= TOL
 

@@ -68,3 +68,46 @@ def test_lieb_liniger_workload(sparse):
     for gamma, lst in by_gamma.items():
         es = [e for _, e in sorted(lst)]
         assert all(b <= a + 1e-9 for a, b in zip(es, es[1:])), gamma
+
+
+def test_paper_truncation_n5_up_to_21_plane_waves(mc):
+    """Sec. VI, Fig. LiebComparison: N = 5 bosons in windows of 11, 13, ...,
+    21 plane waves (M > 8 runs the run-time-M apply; dim 53,130 at M = 21).
+    Energies are variational (>= the Bethe-ansatz value) and non-increasing
+    over the nested windows.  Beyond M = 11 (checked against the oracle's
+    Lanczos above) the values are otherwise parity unpinned."""
+    from paper_2005_13679_amd import lanczos
+    N, c = 5, 10.0
+    e_ba = bethe.ground_energy(N, c)
+    energies = []
+    for M in range(11, 22, 2):
+        h, g = W.lieb_liniger_h(M), W.lieb_liniger_g(M, c)
+        tab = mc.build_tables(N, M)
+        v0 = W.random_coefficients(np.random.default_rng(50 + M), tab.dim)
+        e, *_ = lanczos.ground_state(h, g, tab, dev(v0), max_iter=400, tol=1e-13)
+        print(f"[ll] N={N} M={M} dim={tab.dim}: E0 = {e:.10f} (Bethe ansatz {e_ba:.10f})",
+              flush=True)
+        assert e >= e_ba - 1e-9
+        energies.append(e)
+        del tab
+    assert all(b <= a + 1e-9 for a, b in zip(energies, energies[1:]))
+
+
+def test_paper_truncation_n20_nine_plane_waves(mc):
+    """N = 20, M = 9 (dim 3,108,105), gamma = 1: below the stored M = 7
+    energy and above the Bethe-ansatz value (the M = 9 point of the trend;
+    parity unpinned beyond these bounds)."""
+    from paper_2005_13679_amd import lanczos
+    ref = json.load(open(os.path.join(GOLDEN, "ll_energies.json")))
+    r7 = next(r for r in ref["runs"] if r["gamma"] == 1.0 and r["M"] == 7)
+    N, M, L, c = ref["N"], 9, ref["L"], r7["c"]
+    h, g = W.lieb_liniger_h(M, L), W.lieb_liniger_g(M, c, L)
+    tab = mc.build_tables(N, M)   # M > 8: the paper form with its double-jump map
+    assert tab.dim == 3_108_105
+    v0 = W.random_coefficients(np.random.default_rng(9), tab.dim)
+    e, _, _, it = lanczos.ground_state(h, g, tab, dev(v0), max_iter=400, tol=1e-12)
+    print(f"[ll] N={N} M={M}: E0 = {e:.10f} after {it} iterations (M = 7: {r7['E0']:.10f}, "
+          f"Bethe ansatz {r7['E_bethe']:.10f})", flush=True)
+    assert r7["E_bethe"] - 1e-9 <= e <= r7["E0"] + 1e-9
+    del tab
+    torch.cuda.empty_cache()

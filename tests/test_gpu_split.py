@@ -7,7 +7,7 @@ import pytest
 import torch
 
 import workloads as W
-from tests.gpu_helpers import rel_inf
+from tests.gpu_helpers import ORDER_TOL, rel_inf
 
 pytestmark = pytest.mark.gpu
 
@@ -34,8 +34,8 @@ def test_split_apply_matches_oracle(mc, oracle_native, N, M, seed):
     a = mc.apply_H(dev(h), dev(g), dev(C), tm)
     b = mc.apply_H(dev(h), dev(g), dev(C), tc)
     assert rel_inf(a.cpu().numpy(), ref) <= TOL
-    # both sources of the true double jumps accumulate in the same order
-    assert torch.equal(a, b)
+    # both sources of the true double jumps give the same sums
+    assert rel_inf(a.cpu().numpy(), b.cpu().numpy()) <= ORDER_TOL
 
 
 @pytest.mark.parametrize("N,M", [(4, 3), (10, 5), (6, 6), (5, 8), (3, 2)])
