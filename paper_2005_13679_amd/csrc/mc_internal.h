@@ -194,20 +194,22 @@ __device__ __forceinline__ int wave_in_block()
     return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 }
 
-// Maps a hardware block index to a logical one.  With MC_XCD_REMAP = 1 each
-// of the 8 XCDs (which receive blocks round-robin) works on a contiguous
-// range of blocks, so neighbouring tiles share the XCD's L2.  For the H.C
-// gathers the identity is faster (measured 2-8 %): an XCD's L2 cannot hold
-// the coefficient windows of its range anyway, and interleaved blocks let the
-// 8 XCDs share one working set in the memory-side cache.
+// Maps a hardware block index to a logical one.  The 8 XCDs receive blocks
+// round-robin.  With MC_XCD_REMAP = 1 each XCD works on one contiguous range
+// of blocks; with MC_XCD_CHUNK = K > 1 (the default, remap off) each XCD takes
+// contiguous chunks of K blocks, the chunks interleaved over the XCDs (blocks
+// past the last whole group of 8K map to themselves).  Neighbouring tiles
+// gather from overlapping coefficient windows, so chunks let one XCD's L2
+// serve them, while interleaved chunks keep all XCDs in one region of the
+// index space, whose windows the memory-side cache then shares.  Measured at
+// N=200, M=5 against the identity (K = 1) and the full remap: K = 512 is
+// 3 % (reduced map), 1.5 % (paper map), 6 % (no table) and 15 % (chained)
+// faster than the identity; the full remap is 2-8 % slower than it.
 #ifndef MC_XCD_REMAP
 #define MC_XCD_REMAP 0
 #endif
-// MC_XCD_CHUNK = K > 1 (with the remap off): each XCD takes contiguous chunks
-// of K blocks, chunks interleaved over the XCDs (blocks past the last whole
-// group of 8K map to themselves).
 #ifndef MC_XCD_CHUNK
-#define MC_XCD_CHUNK 1
+#define MC_XCD_CHUNK 512
 #endif
 __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb)
 {
