@@ -86,8 +86,8 @@ def algorithmic_bytes(N: int, M: int, path: str = "reduced_map") -> dict:
 # what the counters show limits each path's apply kernel (the HBM roofline is
 # the one that bounds the byte model; these kernels stop short of it)
 LIMITERS = {
-    "reduced_map": "coefficient re-fetch beyond the L2: about 68 GB of HBM-side traffic per "
-                   "apply (1.7x the byte model) at about 0.86 of peak (rocprofv3 FETCH_SIZE)",
+    "reduced_map": "latency of the coefficient gathers through L1/TA (HBM-side traffic 46.5 GB "
+                   "per apply, 1.17x the byte model, at 4.8 TB/s: rocprofv3 FETCH_SIZE)",
     "reduced_chained": "coefficient gathers through L1/TA (chained second hops)",
     "paper_map": "coefficient gathers through L1/TA (375 double-jump slots per row)",
     "paper_chained": "coefficient gathers through L1/TA (chained second hops)",

@@ -246,7 +246,8 @@ void k_batch_solo(int N, int nbits, int64_t D, int64_t tiles, int64_t nblocks, i
                   double2 *__restrict__ HC)
 {
     __shared__ double sq[kLdsRoots<MT> ? kBatchMaxN + 3 : 1];
-    if constexpr (kLdsRoots<MT>) fill_sqrt_table(sq, kBatchMaxN + 3);
+    // one instance: the roots it needs, as the plain launch fills them
+    if constexpr (kLdsRoots<MT>) fill_sqrt_table(sq, N + 3 < kBatchMaxN + 3 ? N + 3 : kBatchMaxN + 3);
     const int64_t tile =
         xcd_block_as<KIND == kDirect && kDirectRemap<MT>>(blockIdx.x, nblocks) * 4 + wave_in_block();
     if (tile >= tiles) return;

@@ -523,8 +523,8 @@ __host__ __device__ constexpr int prefix_delta(int m, int R1, int R2, int A1, in
            (R2 >= 0 && R2 <= m);
 }
 
-// Removed (R1, R2) and created (A1, A2) orbitals of slot U of the flat
-// stream (-1: none); U = -1 is the row itself.
+// Removed (R1, R2) and created (A1, A2) orbitals of slot U of the case-split
+// flat stream (-1: none); U = -1 is the row itself.
 template <int MT>
 __host__ __device__ constexpr void flat_jump(int U, int &R1, int &R2, int &A1, int &A2)
 {
@@ -544,14 +544,6 @@ __host__ __device__ constexpr void flat_jump(int U, int &R1, int &R2, int &A1, i
     A2 = reduced_ql(MT, R1, R2, r, 1);
 }
 
-template <int MT>
-__host__ __device__ constexpr int flat_delta(int U, int m)
-{
-    int R1 = 0, R2 = 0, A1 = 0, A2 = 0;
-    flat_jump<MT>(U, R1, R2, A1, A2);
-    return prefix_delta(m, R1, R2, A1, A2);
-}
-
 #ifndef MC_CLASS_STREAM
 #define MC_CLASS_STREAM 1
 #endif
@@ -559,12 +551,34 @@ __host__ __device__ constexpr int flat_delta(int U, int m)
 #define MC_CLASS_BATCH 16
 #endif
 
-// The stream in class-major order: position i holds flat slot slot[i] (-1:
-// the row itself), whose value is the anchor at position anc[i] read from
-// lane + sh[i]; batches of whole classes of at most MC_CLASS_BATCH positions.
-template <int MT>
-struct ClassPlan {
+// Slot stream of a full tile.  Form 0: the case-split sum (single jumps,
+// then the true double jumps of the reduced map).  (The paper's sum, every
+// slot of every removal pair, walked the same way measured no faster: that
+// kernel is bound by its 111 GB table stream and its register use.)
+template <int MT, int FORM>
+struct SlotForm {
+    static_assert(FORM == 0, "class-major stream of the case-split sum only");
     static constexpr int U = FlatTile<MT>::U;
+    static constexpr void jump(int u, int &R1, int &R2, int &A1, int &A2)
+    {
+        flat_jump<MT>(u, R1, R2, A1, A2);
+    }
+    static constexpr int delta(int u, int m)
+    {
+        int R1 = 0, R2 = 0, A1 = 0, A2 = 0;
+        jump(u, R1, R2, A1, A2);
+        return prefix_delta(m, R1, R2, A1, A2);
+    }
+};
+
+// The stream in class-major order: position i holds slot slot[i] (-1: the
+// row itself), whose value is the anchor at position anc[i] read from
+// lane + sh[i]; batches of whole classes of at most MC_CLASS_BATCH
+// positions (a larger class is cut into parts, each with an anchor of its
+// own).
+template <int MT, int FORM>
+struct ClassPlan {
+    static constexpr int U = SlotForm<MT, FORM>::U;
     static constexpr int NP = U + 1;
     int slot[NP] = {};
     int anc[NP] = {};
@@ -578,28 +592,35 @@ struct ClassPlan {
         // Delta_0 and the class key (Delta_1 .. Delta_{M-2}, base 5) of each slot
         int d0[NP] = {}, key[NP] = {};
         for (int v = -1; v < U; ++v) {
-            d0[v + 1] = flat_delta<MT>(v, 0);
+            d0[v + 1] = SlotForm<MT, FORM>::delta(v, 0);
             int k = 0;
-            for (int m = MT - 2; m >= 1; --m) k = 5 * k + flat_delta<MT>(v, m) + 2;
+            for (int m = MT - 2; m >= 1; --m) k = 5 * k + SlotForm<MT, FORM>::delta(v, m) + 2;
             key[v + 1] = k;
         }
         bool used[NP] = {};
         int pos = 0;
         for (int a = -1; a < U; ++a) {
             if (used[a + 1]) continue;
-            // a opens a class: it and every later slot of its class
-            const int first = pos;
+            // a opens a class: it and every later slot of its class, in parts
+            // of at most MC_CLASS_BATCH
+            int first = pos, part = 0, lead = a;
             for (int v = a; v < U; ++v) {
                 if (used[v + 1] || key[v + 1] != key[a + 1]) continue;
+                if (part == MC_CLASS_BATCH) {
+                    first = pos;
+                    part = 0;
+                    lead = v;
+                }
                 used[v + 1] = true;
                 slot[pos] = v;
                 anc[pos] = first;
-                sh[pos] = d0[a + 1] - d0[v + 1];
+                sh[pos] = d0[lead + 1] - d0[v + 1];
+                if (pos == first && v >= 0) ++anchors;
                 ++pos;
+                ++part;
             }
-            if (a >= 0) ++anchors;
         }
-        // greedy batches of whole classes
+        // greedy batches of whole parts
         int start = 0;
         nb = 0;
         bstart[0] = 0;
@@ -617,9 +638,8 @@ struct ClassPlan {
     }
 };
 
-template <int MT>
-constexpr ClassPlan<MT> kClassPlan{};
-
+template <int MT, int FORM>
+constexpr ClassPlan<MT, FORM> kClassPlan{};
 
 // x moved s lanes: lane i receives lane i + s (s > 0: wave_shl, s < 0:
 // wave_shr, one lane per step); lanes with no source get `fill`.
@@ -638,46 +658,62 @@ __device__ __forceinline__ int32_t lane_shift_i32(int32_t x, int32_t fill)
 template <int S>
 __device__ __forceinline__ double2 lane_shift_c128(double2 v)
 {
-    int32_t w[4];
-    __builtin_memcpy(w, &v, 16);
+    if constexpr (S == 0) {
+        return v;
+    } else {
+        int32_t w[4];
+        __builtin_memcpy(w, &v, 16);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) w[k] = lane_shift_i32<S>(w[k], 0);
-    double2 r;
-    __builtin_memcpy(&r, w, 16);
-    return r;
+        for (int k = 0; k < 4; ++k) w[k] = lane_shift_i32<S>(w[k], 0);
+        double2 r;
+        __builtin_memcpy(&r, w, 16);
+        return r;
+    }
 }
 
-// Arithmetic of one slot in the class-major order: a single jump adds
+// Constants and arithmetic of one slot: a single jump adds
 // sqrt(n_a (n_b+1)) [HS_ab + sum_c n_c GS_abc] C, a true double jump
-// A_KS B_ql GD C (A folded per slot, as the slots of a pair are no longer
+// A_KS B_ql GD C (A folded per slot, as the slots of a pair are not
 // adjacent).
-template <int MT, int U>
-__device__ __forceinline__ void class_fma(const double2 &c, const RowSq<MT> &R,
-                                          const double (&x)[MT], const double2 *__restrict__ HS,
-                                          const double2 *__restrict__ GS,
-                                          const double2 *__restrict__ GD, double &ar, double &ai)
+template <int MT, int FORM>
+struct ClassConsts;
+
+template <int MT>
+struct ClassConsts<MT, 0> {
+    const double2 *__restrict__ HS;
+    const double2 *__restrict__ GS;
+    const double2 *__restrict__ GD;
+    const double (&x)[MT];
+};
+
+
+__device__ __forceinline__ void cmac(double er, double ei, const double2 &c, double &ar, double &ai)
 {
-    constexpr int NSING = FlatTile<MT>::NSING;
+    ar = fma(er, c.x, ar);
+    ar = fma(-ei, c.y, ar);
+    ai = fma(er, c.y, ai);
+    ai = fma(ei, c.x, ai);
+}
+
+template <int MT, int FORM, int U>
+__device__ __forceinline__ void class_fma(const double2 &c, const RowSq<MT> &R,
+                                          const ClassConsts<MT, FORM> &k, double &ar, double &ai)
+{
+    constexpr int NSING = MT * (MT - 1);
     if constexpr (U < 0) {
         return;   // the row itself: its term is added before the stream
     } else if constexpr (U < NSING) {
         constexpr int a = U / (MT - 1), bb = U % (MT - 1), b = bb + (bb >= a), j = a * MT + b;
-        double er = HS[j].x, ei = HS[j].y;
-#pragma unroll
-        for (int k = 0; k < MT; ++k) {
-            er = fma(GS[j * MT + k].x, x[k], er);
-            ei = fma(GS[j * MT + k].y, x[k], ei);
-        }
         const double f = R.template root<0>(a) * R.template root<1>(b);
-        er *= f;
-        ei *= f;
-        ar = fma(er, c.x, ar);
-        ar = fma(-ei, c.y, ar);
-        ai = fma(er, c.y, ai);
-        ai = fma(ei, c.x, ai);
+        double er = k.HS[j].x, ei = k.HS[j].y;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            er = fma(k.GS[j * MT + m].x, k.x[m], er);
+            ei = fma(k.GS[j * MT + m].y, k.x[m], ei);
+        }
+        cmac(er * f, ei * f, c, ar, ai);
     } else {
-        constexpr int e = U - NSING;
-        constexpr int P = flat_pair(MT, e), r = flat_slot(MT, e);
+        constexpr int P = flat_pair(MT, U - NSING), r = flat_slot(MT, U - NSING);
         constexpr int K = pair_k(MT, P), S = pair_s(MT, P);
         constexpr int q = reduced_ql(MT, K, S, r, 0), l = reduced_ql(MT, K, S, r, 1);
         const double Bf = q == l ? R.template root<1>(q) * R.template root<2>(q)
@@ -686,7 +722,7 @@ __device__ __forceinline__ void class_fma(const double2 &c, const RowSq<MT> &R,
                          (K == S ? R.template root<-1>(K) : R.template root<0>(S));
         const double w = A * Bf;
         const double cr = c.x * w, ci = c.y * w;
-        const double2 Gv = GD[e];
+        const double2 Gv = k.GD[U - NSING];
         ar = fma(Gv.x, cr, ar);
         ar = fma(-Gv.y, ci, ar);
         ai = fma(Gv.x, ci, ai);
@@ -698,16 +734,14 @@ __device__ __forceinline__ void class_fma(const double2 &c, const RowSq<MT> &R,
 // batch's target indices (from the source: table loads or closed form).
 // Anchor gathers and the members' edge re-gathers are issued together, then
 // the shifts, then the arithmetic.
-template <int MT, bool BIGC, int B, int... Is>
+template <int MT, int FORM, bool BIGC, int B, int... Is>
 __device__ __forceinline__ void class_batch(std::integer_sequence<int, Is...>,
                                             const int32_t (&tix)[MC_CLASS_BATCH], int32_t own_t,
                                             double2 own_c, const RowSq<MT> &R,
-                                            const double (&x)[MT], const double2 *__restrict__ HS,
-                                            const double2 *__restrict__ GS,
-                                            const double2 *__restrict__ GD,
+                                            const ClassConsts<MT, FORM> &k,
                                             const Gather<BIGC> &ldc, double &ar, double &ai)
 {
-    constexpr ClassPlan<MT> cp = kClassPlan<MT>;
+    constexpr ClassPlan<MT, FORM> cp = kClassPlan<MT, FORM>;
     constexpr int I0 = cp.bstart[B], I1 = cp.bstart[B + 1];
     double2 v[MC_CLASS_BATCH];
     // anchors: gather (the row itself: its own coefficient)
@@ -747,18 +781,18 @@ __device__ __forceinline__ void class_batch(std::integer_sequence<int, Is...>,
     (
         [&] {
             constexpr int i = I0 + Is;
-            if constexpr (i < I1) class_fma<MT, cp.slot[i]>(v[Is], R, x, HS, GS, GD, ar, ai);
+            if constexpr (i < I1) class_fma<MT, FORM, cp.slot[i]>(v[Is], R, k, ar, ai);
         }(),
         ...);
 }
 
 // Target index of class-major position i from the source (the row itself
 // needs none).
-template <int MT, int B, class Src, int... Is>
+template <int MT, int FORM, int B, class Src, int... Is>
 __device__ __forceinline__ void class_targets(std::integer_sequence<int, Is...>, const Src &src,
                                               int32_t (&tix)[MC_CLASS_BATCH])
 {
-    constexpr ClassPlan<MT> cp = kClassPlan<MT>;
+    constexpr ClassPlan<MT, FORM> cp = kClassPlan<MT, FORM>;
     constexpr int I0 = cp.bstart[B], I1 = cp.bstart[B + 1];
     (
         [&] {
@@ -770,52 +804,53 @@ __device__ __forceinline__ void class_targets(std::integer_sequence<int, Is...>,
 
 // The whole stream: batch B's block issues batch B+1's targets (table loads
 // in flight during B's gathers), then B's gathers and arithmetic.
-template <int MT, bool BIGC, int B, class Src>
+template <int MT, int FORM, bool BIGC, int B, class Src>
 __device__ __forceinline__ void class_batches(int32_t (&cur)[MC_CLASS_BATCH],
                                               int32_t (&nxt)[MC_CLASS_BATCH], const Src &src,
                                               int32_t own_t, double2 own_c, const RowSq<MT> &R,
-                                              const double (&x)[MT],
-                                              const double2 *__restrict__ HS,
-                                              const double2 *__restrict__ GS,
-                                              const double2 *__restrict__ GD,
+                                              const ClassConsts<MT, FORM> &k,
                                               const Gather<BIGC> &ldc, double &ar, double &ai)
 {
-    constexpr int NB = kClassPlan<MT>.nb;
+    constexpr int NB = kClassPlan<MT, FORM>.nb;
     if constexpr (B < NB) {
         // each batch in a basic block of its own (see opaque_true)
         if (opaque_true()) {
             if constexpr (B + 1 < NB)
-                class_targets<MT, B + 1>(std::make_integer_sequence<int, MC_CLASS_BATCH>{}, src, nxt);
-            class_batch<MT, BIGC, B>(std::make_integer_sequence<int, MC_CLASS_BATCH>{}, cur, own_t,
-                                     own_c, R, x, HS, GS, GD, ldc, ar, ai);
+                class_targets<MT, FORM, B + 1>(std::make_integer_sequence<int, MC_CLASS_BATCH>{},
+                                               src, nxt);
+            class_batch<MT, FORM, BIGC, B>(std::make_integer_sequence<int, MC_CLASS_BATCH>{}, cur,
+                                           own_t, own_c, R, k, ldc, ar, ai);
         }
-        class_batches<MT, BIGC, B + 1>(nxt, cur, src, own_t, own_c, R, x, HS, GS, GD, ldc, ar, ai);
+        class_batches<MT, FORM, BIGC, B + 1>(nxt, cur, src, own_t, own_c, R, k, ldc, ar, ai);
     }
 }
 
-template <int MT, bool BIGC, class Src>
+template <int MT, int FORM, bool BIGC, class Src>
 __device__ __forceinline__ void class_stream(const Src &src, int32_t own_t, double2 own_c,
-                                             const RowSq<MT> &R, const double (&x)[MT],
-                                             const double2 *__restrict__ HS,
-                                             const double2 *__restrict__ GS,
-                                             const double2 *__restrict__ GD,
+                                             const RowSq<MT> &R, const ClassConsts<MT, FORM> &k,
                                              const Gather<BIGC> &ldc, double &ar, double &ai)
 {
     int32_t ta[MC_CLASS_BATCH], tb[MC_CLASS_BATCH];
-    class_targets<MT, 0>(std::make_integer_sequence<int, MC_CLASS_BATCH>{}, src, ta);
-    class_batches<MT, BIGC, 0>(ta, tb, src, own_t, own_c, R, x, HS, GS, GD, ldc, ar, ai);
+    class_targets<MT, FORM, 0>(std::make_integer_sequence<int, MC_CLASS_BATCH>{}, src, ta);
+    class_batches<MT, FORM, BIGC, 0>(ta, tb, src, own_t, own_c, R, k, ldc, ar, ai);
 }
 
 // Targets of a full tile through the tables: the tile's single-jump block
-// and its reduced-map block.
-template <int MT>
+// and its reduced-map block (every pair present, in order).
+template <int MT, int FORM>
 struct MapSlots {
     __amdgpu_buffer_rsrc_t r1, r2;
     int lane;
     template <int U>
     __device__ __forceinline__ int32_t target() const
     {
-        return flat_load<MT, U>(r1, r2, lane);
+        constexpr int NSING = MT * (MT - 1);
+        if constexpr (U < NSING) {
+            constexpr int a = U / (MT - 1), bb = U % (MT - 1), b = bb + (bb >= a);
+            return buf_ld_i32(r1, (uint32_t)(((a * MT + b) * kTile + lane) * 4), 0);
+        } else {
+            return buf_ld_i32(r2, (uint32_t)(((U - NSING) * kTile + lane) * 4), 0);
+        }
     }
 };
 
@@ -888,8 +923,9 @@ __device__ __forceinline__ void apply_tile_split(int64_t tile, int64_t D, int64_
             const __amdgpu_buffer_rsrc_t r2 =
                 make_rsrc(t2r + off0, (uint32_t)(FlatTile<MT>::NDBL * kTile * 4));
 #if MC_CLASS_STREAM
-            const MapSlots<MT> src{r1, r2, lane};
-            class_stream<MT, BIGC>(src, live ? (int32_t)g : -2, cg, R, x, HS, GS, GD, ldc, ar, ai);
+            const MapSlots<MT, 0> src{r1, r2, lane};
+            const ClassConsts<MT, 0> k{HS, GS, GD, x};
+            class_stream<MT, 0, BIGC>(src, live ? (int32_t)g : -2, cg, R, k, ldc, ar, ai);
 #else
             int32_t ta[FlatTile<MT>::SB], tb[FlatTile<MT>::SB];
             flat_loads<MT, 0>(std::make_integer_sequence<int, FlatTile<MT>::SB>{}, ta, r1, r2, lane);
