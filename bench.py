@@ -289,8 +289,9 @@ def sil_leg(dev, N: int = 200, M: int = 5, dt: float = 1e-5, tol: float = 1e-10)
     out2, m2, _ = st.step(Cd, dt, tol=tol, out=out2)
     torch.cuda.synchronize()
     sec2 = time.perf_counter() - t0
+    diff = float(torch.max(torch.abs(out - out2)) / torch.max(torch.abs(out)))
     res["table_free"] = {"krylov_dim": m2, "step_ms": sec2 * 1e3,
-                         "same_result": bool(torch.equal(out, out2))}
+                         "rel_diff_vs_tables": diff}
     del st, out, out2, Cd
     torch.cuda.empty_cache()
     return res

@@ -38,9 +38,10 @@
 //
 // Kernel.  One wavefront per block walks chunks of 64 intermediate
 // configurations (lane = configuration): it computes its row of X into LDS,
-// then the upper triangle of the chunk's Gram matrix is accumulated in 4 x 4
-// complex register blocks, one block pair (bi <= bj) per lane and the 64 rows
-// split over 64 / #blocks lane groups.  The groups are summed in a fixed
+// then the upper triangle of the chunk's Gram matrix is accumulated in
+// BS x BS complex register blocks (BS of 2, 3 or 4: the least padding), one
+// block pair (bi <= bj) per lane and the 64 rows split over 64 / #blocks lane
+// groups.  The groups are summed in a fixed
 // order at the end; partials per wavefront go to the workspace and are summed
 // over wavefronts by a fixed tree: results are bitwise reproducible.
 #pragma once
@@ -57,14 +58,32 @@ namespace mc {
 
 // Column layout of the lift of L particles (L = 1: one column per orbital;
 // L = 2: one per unordered pair, lexicographic).
+// Register block size of the Gram accumulation: of 2, 3 and 4, the one that
+// pads the upper triangle least with at most 64 block pairs (one per lane).
+__host__ __device__ constexpr int gram_block(int P)
+{
+    int best = 4, best_pad = 1 << 30;
+    for (int bs = 2; bs <= 4; ++bs) {
+        const int pb = (P + bs - 1) / bs, nb = pb * (pb + 1) / 2;
+        if (nb > 64) continue;
+        const int pad = nb * bs * bs;
+        if (pad < best_pad) {
+            best = bs;
+            best_pad = pad;
+        }
+    }
+    return best;
+}
+
 template <int MT, int L>
 struct Lift {
     static constexpr int P = L == 1 ? MT : MT * (MT + 1) / 2;   // columns
-    static constexpr int PB = (P + 3) / 4;                        // 4-column blocks
-    static constexpr int PP = 4 * PB;                             // padded columns
+    static constexpr int BS = gram_block(P);                     // register block size
+    static constexpr int PB = (P + BS - 1) / BS;                  // column blocks
+    static constexpr int PP = BS * PB;                            // padded columns
     static constexpr int NB = PB * (PB + 1) / 2;                  // block pairs bi <= bj
     static constexpr int R = 64 / NB;                             // lane groups over rows
-    static constexpr int E = NB * 16;                             // partial entries per wave
+    static constexpr int E = NB * BS * BS;                        // partial entries per wave
     static constexpr int STRIDE = PP + 1;                         // LDS row stride (double2)
     static constexpr int LDS = (64 * STRIDE > 64 * 16 ? 64 * STRIDE : 64 * 16) * 16;   // bytes
 };
@@ -162,17 +181,16 @@ struct LiftTargets {
 
 template <int MT, int L, bool BIGC>
 struct DirectSource {
+    using Tgt = LiftTargets<MT, L>;
     int Nl, nbits;      // N - L and its bit width
     int64_t Dl, DN;     // dimensions of the N - L and N particle spaces
 
-    // row of X for intermediate configuration ch * 64 + lane
-    __device__ __forceinline__ bool fill(int64_t ch, int lane, const Gather<BIGC> &ldc,
-                                         double2 *xrow) const
+    // targets and occupations of intermediate configuration ch * 64 + lane
+    __device__ __forceinline__ bool prepare(int64_t ch, int lane, Tgt &tg, int (&m)[MT]) const
     {
         const int64_t row = ch * 64 + lane;
-        LiftTargets<MT, L> tg;
         tg.live = row < Dl;
-        int S[MT], m[MT];
+        int S[MT];
         direct_prefix<MT>(tg.live ? row : Dl - 1, Dl, Nl, nbits, S);
         m[0] = S[0];
 #pragma unroll
@@ -184,6 +202,16 @@ struct DirectSource {
             for (int d = 0; d <= L; ++d)
                 tg.G[j][d] =
                     j == 0 ? (uint32_t)(S[0] + d) : (uint32_t)direct_g(j, (double)(S[j] + d));
+        return true;
+    }
+
+    // the lane's row of X
+    __device__ __forceinline__ bool fill(int64_t ch, int lane, const Gather<BIGC> &ldc,
+                                         double2 *xrow) const
+    {
+        Tgt tg;
+        int m[MT];
+        prepare(ch, lane, tg, m);
         gram_row<MT, L, BIGC>(std::make_integer_sequence<int, kGramBatches<MT, L>>{}, tg, m, ldc,
                               xrow);
         return true;
@@ -234,6 +262,7 @@ struct MapTargets {
 
 template <int MT, int L, typename OccT, int KIND, bool BIGC>
 struct MapSource {
+    using Tgt = MapTargets<MT, L, KIND>;
     int64_t D, cap;   // rows; capacity of the double-jump map (entries)
     const OccT *__restrict__ occ;
     const int32_t *__restrict__ t1;
@@ -241,19 +270,18 @@ struct MapSource {
     const int64_t *__restrict__ t2_off;
     const int32_t *__restrict__ t2;
 
-    __device__ __forceinline__ bool fill(int64_t tile, int lane, const Gather<BIGC> &ldc,
-                                         double2 *xrow) const
+    // targets and occupations of the rows of tile `tile` (false: no row of
+    // the tile has L particles in orbital 0; wave-uniform)
+    __device__ __forceinline__ bool prepare(int64_t tile, int lane, Tgt &tg, int (&m)[MT]) const
     {
         constexpr int NS = MT * MT;
-        MapTargets<MT, L, KIND> tg;
         tg.lane = lane;
         tg.t1 = t1;
         const int64_t g = tile * kTile + lane;
-        int n[MT], m[MT];
+        int n[MT];
 #pragma unroll
         for (int k = 0; k < MT; ++k) n[k] = (int)occ[(tile * MT + k) * kTile + lane];
         tg.live = g < D && n[0] >= L;
-        if (!__builtin_amdgcn_readfirstlane(__ballot(tg.live) != 0)) return false;
         tg.g = (int32_t)g;
         // occupations of m = n - L e_0 (zero on rows without one: their
         // amplitudes must stay finite, their values are zero)
@@ -273,11 +301,50 @@ struct MapSource {
             tg.r2 = make_rsrc(t2 + (fits ? off0 : 0), fits ? (uint32_t)(BS * kTile * 4) : 0u);
             if (!fits) tg.live = false;
         }
+        return __builtin_amdgcn_readfirstlane(__ballot(tg.live) != 0);
+    }
+
+    __device__ __forceinline__ bool fill(int64_t tile, int lane, const Gather<BIGC> &ldc,
+                                         double2 *xrow) const
+    {
+        Tgt tg;
+        int m[MT];
+        if (!prepare(tile, lane, tg, m)) return false;
         gram_row<MT, L, BIGC>(std::make_integer_sequence<int, kGramBatches<MT, L>>{}, tg, m, ldc,
                               xrow);
         return true;
     }
 };
+
+// Prefetch form of a row of X: every column's gather issued at once (values
+// in registers), and later the amplitudes applied into LDS.
+template <int MT, int L, bool BIGC, class Tgt, int... Cs>
+__device__ __forceinline__ void gram_issue(std::integer_sequence<int, Cs...>, const Tgt &tgt,
+                                           const Gather<BIGC> &ldc,
+                                           double2 (&v)[Lift<MT, L>::P])
+{
+    int32_t t[sizeof...(Cs)];
+    ((t[Cs] = tgt.template target<col_q<MT, L, Cs>(), col_l<MT, L, Cs>()>()), ...);
+    ((v[Cs] = ldc(t[Cs])), ...);
+}
+
+template <int MT, int L, int... Cs>
+__device__ __forceinline__ void gram_commit(std::integer_sequence<int, Cs...>, const int (&m)[MT],
+                                            const double2 (&v)[Lift<MT, L>::P], double2 *xrow)
+{
+    (
+        [&] {
+            const double a = lift_amp<MT, col_q<MT, L, Cs>(), col_l<MT, L, Cs>()>(m);
+            xrow[Cs] = make_double2(a * v[Cs].x, a * v[Cs].y);
+        }(),
+        ...);
+}
+
+// Up to this many columns the next chunk's gathers are kept in registers
+// while the current chunk's Gram matrix is accumulated.
+#ifndef MC_GRAM_PREFETCH_MAX_P
+#define MC_GRAM_PREFETCH_MAX_P 21
+#endif
 
 // ---------------------------------------------------------------------------
 // The Gram kernel over any source.
@@ -301,29 +368,52 @@ __global__ __launch_bounds__(64) void k_gram(Src src, int64_t DN, int64_t chunks
         ++bi;
     }
     const int bj = bi + rem;
-    double ar[4][4], ai[4][4];
+    constexpr int BS = LF::BS;
+    double ar[BS][BS], ai[BS][BS];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < BS; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) ar[i][j] = ai[i][j] = 0.0;
+        for (int j = 0; j < BS; ++j) ar[i][j] = ai[i][j] = 0.0;
     const Gather<BIGC> ldc(C, DN);
+    constexpr bool PRE = LF::P <= MC_GRAM_PREFETCH_MAX_P;
+    typename Src::Tgt tg;
+    int m[MT];
+    double2 pv[PRE ? LF::P : 1];
+    if constexpr (PRE) {
+        if (wave < chunks) {
+            src.prepare(wave, lane, tg, m);
+            gram_issue<MT, L, BIGC>(std::make_integer_sequence<int, LF::P>{}, tg, ldc, pv);
+        }
+    }
     for (int64_t ch = wave; ch < chunks; ch += nwaves) {
-        // a chunk with no intermediate configuration adds nothing (wave-uniform)
-        if (!src.fill(ch, lane, ldc, X + lane * LF::STRIDE)) continue;
-        __syncthreads();
+        if constexpr (PRE) {
+            // this chunk's values (in flight since the last chunk) into LDS,
+            // then the next chunk's gathers, in flight during the arithmetic
+            gram_commit<MT, L>(std::make_integer_sequence<int, LF::P>{}, m, pv,
+                               X + lane * LF::STRIDE);
+            __syncthreads();
+            if (ch + nwaves < chunks) {
+                src.prepare(ch + nwaves, lane, tg, m);
+                gram_issue<MT, L, BIGC>(std::make_integer_sequence<int, LF::P>{}, tg, ldc, pv);
+            }
+        } else {
+            // a chunk with no intermediate configuration adds nothing (wave-uniform)
+            if (!src.fill(ch, lane, ldc, X + lane * LF::STRIDE)) continue;
+            __syncthreads();
+        }
         if (grp < LF::R) {
             for (int r = grp; r < 64; r += LF::R) {
                 const double2 *xr = X + r * LF::STRIDE;
-                double2 a[4], b[4];
+                double2 a[BS], b[BS];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    a[i] = xr[4 * bi + i];
-                    b[i] = xr[4 * bj + i];
+                for (int i = 0; i < BS; ++i) {
+                    a[i] = xr[BS * bi + i];
+                    b[i] = xr[BS * bj + i];
                 }
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
+                for (int i = 0; i < BS; ++i)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
+                    for (int j = 0; j < BS; ++j) {
                         // conj(a_i) b_j
                         ar[i][j] = fma(a[i].x, b[j].x, fma(a[i].y, b[j].y, ar[i][j]));
                         ai[i][j] = fma(a[i].x, b[j].y, fma(-a[i].y, b[j].x, ai[i][j]));
@@ -335,16 +425,16 @@ __global__ __launch_bounds__(64) void k_gram(Src src, int64_t DN, int64_t chunks
     // sum the lane groups of each block pair in group order
     if (grp < LF::R) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < BS; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                X[(grp * LF::NB + blk) * 16 + i * 4 + j] = make_double2(ar[i][j], ai[i][j]);
+            for (int j = 0; j < BS; ++j)
+                X[(grp * LF::NB + blk) * BS * BS + i * BS + j] = make_double2(ar[i][j], ai[i][j]);
     }
     __syncthreads();
     for (int e = lane; e < LF::E; e += 64) {
         double sr = 0.0, si = 0.0;
         for (int g = 0; g < LF::R; ++g) {
-            const double2 v = X[g * LF::NB * 16 + e];
+            const double2 v = X[g * LF::E + e];
             sr += v.x;
             si += v.y;
         }
@@ -390,7 +480,7 @@ __device__ __forceinline__ int upair(int M, int x, int y)
 // Gram entry (k, l); rho2[k][s][q][l] is entry ({k,s}, {q,l}).  Entries
 // below the diagonal are conjugates, diagonal entries are real.  canon =
 // NULL writes zeros (fewer than L particles).
-__global__ __launch_bounds__(256) void k_gram_expand(int M, int L, int PB,
+__global__ __launch_bounds__(256) void k_gram_expand(int M, int L, int PB, int BS,
                                                      const double2 *__restrict__ canon,
                                                      double2 *__restrict__ out)
 {
@@ -412,9 +502,9 @@ __global__ __launch_bounds__(256) void k_gram_expand(int M, int L, int PB,
     }
     const bool swap = c1 > c2;
     const int x = swap ? c2 : c1, y = swap ? c1 : c2;
-    const int bi = x >> 2, bj = y >> 2;
+    const int bi = x / BS, bj = y / BS;
     const int blk = bi * PB - bi * (bi - 1) / 2 + (bj - bi);
-    double2 v = canon[blk * 16 + (x & 3) * 4 + (y & 3)];
+    double2 v = canon[blk * BS * BS + (x % BS) * BS + (y % BS)];
     if (swap) v.y = -v.y;
     if (x == y) v.y = 0.0;
     out[idx] = v;
@@ -426,7 +516,7 @@ constexpr int64_t kGramMaxWaves = 2048;
 // wavefronts of 256 CUs, at most 8 per CU, fixed per (N, M) so results are
 // reproducible on any device), partial entries, workspace bytes.
 struct GramShape {
-    int64_t chunks = 0, nwaves = 0, E = 0, PB = 0;
+    int64_t chunks = 0, nwaves = 0, E = 0, PB = 0, BS = 0;
     size_t lds = 0, ws = 0;
 };
 
@@ -441,6 +531,7 @@ void gram_shape_t(int64_t chunks, GramShape *g)
     g->nwaves = chunks < w ? (chunks > 0 ? chunks : 1) : w;
     g->E = Lift<MT, L>::E;
     g->PB = Lift<MT, L>::PB;
+    g->BS = Lift<MT, L>::BS;
     g->lds = Lift<MT, L>::LDS;
     g->ws = (size_t)(g->E * g->nwaves + g->E) * 16;
 }
@@ -459,7 +550,7 @@ inline int gram_shape(int M, int L, int64_t chunks, GramShape *g)
 inline int gram_zero(int M, int L, double *out_d, hipStream_t s)
 {
     const int total = L == 1 ? M * M : M * M * M * M;
-    hipLaunchKernelGGL(k_gram_expand, dim3((total + 255) / 256), dim3(256), 0, s, M, L, 1,
+    hipLaunchKernelGGL(k_gram_expand, dim3((total + 255) / 256), dim3(256), 0, s, M, L, 1, 1,
                        (const double2 *)nullptr, (double2 *)out_d);
     return launch_status();
 }
@@ -477,7 +568,7 @@ int gram_launch(const Src &src, int64_t DN, const GramShape &gs, const double *C
     hipLaunchKernelGGL(k_gram_sum, dim3((unsigned)gs.E), dim3(256), 0, s, (int)gs.nwaves, part,
                        canon);
     hipLaunchKernelGGL(k_gram_expand, dim3((total + 255) / 256), dim3(256), 0, s, MT, L,
-                       (int)gs.PB, (const double2 *)canon, (double2 *)out_d);
+                       (int)gs.PB, (int)gs.BS, (const double2 *)canon, (double2 *)out_d);
     return launch_status();
 }
 
