@@ -83,13 +83,59 @@ def algorithmic_bytes(N: int, M: int, path: str = "reduced_map") -> dict:
     return parts
 
 
+def stream_bytes(mc, tab) -> dict:
+    """Bytes the apply kernel must move, each once, through the double-jump
+    map of `tab` (either form, tiled layout): on a tile where every removal
+    pair occurs and the double-jump block is complete, only the class
+    anchors' table columns (mc.apply_stream_columns: the other jumps' targets
+    follow from the anchors' by index arithmetic along runs); on the other
+    tiles every single-jump column and the tile's whole double-jump block;
+    plus the occupations, the tile masks and offsets, and the coefficients
+    in and out."""
+    import torch
+    M, D, tiles = tab.M, tab.dim, tab.tiles
+    slots, cols = mc.apply_stream_columns(M, tab.form)
+    nsing = M * (M - 1)
+    P = M * (M + 1) // 2
+    W = (P + 63) // 64
+    off = tab.t2_off[: tiles + 1]
+    blk = off[1:] - off[:-1]
+    full = blk == (slots - nsing) * 64
+    pm = tab.pmask[: tiles * W].reshape(tiles, W)
+    for w in range(W):
+        bits = min(64, P - 64 * w)
+        want = -1 if bits == 64 else (1 << bits) - 1
+        full &= pm[:, w] == want
+    nfull = int(full.sum().item()) if 2 <= M <= 5 else 0
+    partial_blk = int(blk.sum().item()) - (int(blk[full].sum().item()) if nfull else 0)
+    table = 4 * 64 * (nfull * cols + (tiles - nfull) * nsing) + 4 * partial_blk
+    parts = {
+        "table_columns_read": table,
+        "occupations": tab.occ.numel() * tab.occ.element_size(),
+        "tile_masks_offsets": 8 * (tiles * W + tiles + 1),
+        "coefficients_in": 16 * D,
+        "coefficients_out": 16 * D,
+        "full_tiles": nfull,
+        "tiles": tiles,
+        "anchor_columns": cols,
+        "slots": slots,
+    }
+    parts["total"] = sum(v for k, v in parts.items()
+                         if k not in ("full_tiles", "tiles", "anchor_columns", "slots"))
+    del torch
+    return parts
+
+
 # what the counters show limits each path's apply kernel (the HBM roofline is
 # the one that bounds the byte model; these kernels stop short of it)
 LIMITERS = {
-    "reduced_map": "latency of the coefficient gathers through L1/TA (HBM-side traffic 46.5 GB "
-                   "per apply, 1.17x the byte model, at 4.8 TB/s: rocprofv3 FETCH_SIZE)",
+    "reduced_map": "texture data path (99 % busy, 37 % of it waiting on L1 misses of the anchor "
+                   "gathers) and vector ALU (2,800 instructions per tile, about 70 % of the "
+                   "cycles): 195 vector memory reads per tile; HBM-side traffic 27.1 GB per apply "
+                   "at 3.3 TB/s (rocprofv3 FETCH_SIZE)",
     "reduced_chained": "coefficient gathers through L1/TA (chained second hops)",
-    "paper_map": "coefficient gathers through L1/TA (375 double-jump slots per row)",
+    "paper_map": "vector ALU (the paper's 395 slots of arithmetic per row on 131 gathered "
+                 "targets) and the anchor gathers",
     "paper_chained": "coefficient gathers through L1/TA (chained second hops)",
     "direct": "vector ALU (closed-form targets and amplitudes) and coefficient gathers",
 }
@@ -122,7 +168,7 @@ def rho_models(N: int, M: int) -> dict:
 KERNEL_SOURCES = {
     "reduced_map": ("mc_ops.hip", "mc_internal.h", "mc_apply.h", "mc_split.h"),
     "reduced_chained": ("mc_ops.hip", "mc_internal.h", "mc_apply.h", "mc_split.h"),
-    "paper_map": ("mc_ops.hip", "mc_internal.h", "mc_apply.h"),
+    "paper_map": ("mc_ops.hip", "mc_internal.h", "mc_apply.h", "mc_split.h"),
     "paper_chained": ("mc_ops.hip", "mc_internal.h", "mc_apply.h"),
     "direct": ("mc_ops.hip", "mc_internal.h", "mc_apply.h", "mc_split.h", "mc_direct.h"),
 }
@@ -511,6 +557,8 @@ def main(argv=None):
     print(f"[bench] {args.steps} applies ({args.path}): {ms:.3f} ms each", file=sys.stderr, flush=True)
 
     B = algorithmic_bytes(N, M, args.path)
+    if has_map:
+        B = stream_bytes(mc, tab)
     achieved = B["total"] / (ms * 1e-3) / 1e9
     traffic = measured_traffic(N, M, args.path)
     out = {
@@ -544,6 +592,14 @@ def main(argv=None):
             "limiter": LIMITERS[args.path],
         },
         "algorithmic_bytes_per_apply": B["total"],
+        "algorithmic_bytes_parts": B,
+        # the same apply against structure-once models of whole tables (the
+        # kernel reads less; context only, not the roofline)
+        "byte_models": {
+            name: {"bytes": b, "equivalent_GB_per_s": b / (ms * 1e-3) / 1e9}
+            for name, b in (("reduced_tables_once", algorithmic_bytes(N, M, "reduced_map")["total"]),
+                            ("paper_tables_once", algorithmic_bytes(N, M, "paper_map")["total"]))
+        } if has_map else None,
         "table_build_s": build_s,
         "table_bytes": tab_bytes,
     }
@@ -573,7 +629,7 @@ def main(argv=None):
             for _ in range(2):
                 ap2()
             ms2 = _median_ms(lambda: [ap2() for _ in range(5)], 3, stream) / 5
-            B2 = algorithmic_bytes(N, M, name)["total"]
+            B2 = (stream_bytes(mc, t2) if m2 else algorithmic_bytes(N, M, name))["total"]
             others[name] = {"ms_per_apply": ms2, "applies_per_s": 1e3 / ms2,
                             "algorithmic_bytes": B2, "GB_per_s": B2 / (ms2 * 1e-3) / 1e9,
                             "frac_of_hbm_peak": B2 / (ms2 * 1e-3) / 1e9 / HBM_PEAK_GBS,

@@ -247,6 +247,21 @@ int mc_workspace_size(int32_t N, int32_t M, int32_t op, size_t *bytes);
  * HC_d must not overlap C_d (MC_EINVAL).  ws_d: mc_workspace_size(APPLY);
  * the call stages h and G' there, so concurrent calls need separate ws.
  * No symmetry of h or g is assumed. */
+/* Table reads of the apply through a double-jump map (host query, no
+ * device work).  Within a run of rows (consecutive indices that differ by one
+ * particle moved between orbitals 0 and 1, Eq. TotalCost) a jump's target is
+ * the row's index plus a constant of the run and of the jump's class (the
+ * jumps that change the prefix sums S_1 .. S_{M-2} alike), so on a tile where
+ * every removal pair occurs (2 <= M <= 5) the kernel reads from the tables
+ * only one jump per class and derives the others' targets; slots with one
+ * target share one coefficient.  form: MC_FORM_PAPER (single jumps and the
+ * M*M slots of every removal pair) or MC_FORM_REDUCED (single jumps and the
+ * true double jumps).  *slots: jump slots per row; *table_columns: those
+ * read from the tables per such tile.  M outside 2..5: every slot is read
+ * (*table_columns = *slots).  MC_EINVAL for M outside 1..8, an unknown form
+ * or NULL outputs. */
+int mc_apply_stream_columns(int32_t M, int32_t form, int32_t *slots, int32_t *table_columns);
+
 int mc_apply_H(int32_t N, int32_t M, const double *h_d, const double *g_d,
                const mc_tables *t, const double *C_d, double *HC_d,
                void *ws_d, size_t ws_bytes, mc_stream stream);

@@ -15,6 +15,7 @@ from .api import (
     apply_H_adjoint,
     apply_H_direct,
     apply_H_sparse,
+    apply_stream_columns,
     build_tables,
     choose_double_jumps,
     dim,
@@ -37,7 +38,8 @@ from .batch import Batch, BatchedLanczos, batched_lanczos
 from .propagate import SILStepper, sil_step
 
 __all__ = [
-    "MCError", "LIB_PATH", "SILStepper", "sil_step", "Batch", "BatchedLanczos", "batched_lanczos", "Energy", "DirectSpace", "Tables", "apply_H", "apply_H_adjoint", "apply_H_direct", "apply_H_sparse", "energy", "build_tables", "dim", "hash_batch",
+    "MCError", "LIB_PATH", "SILStepper", "sil_step", "Batch", "BatchedLanczos", "batched_lanczos", "Energy", "DirectSpace", "Tables", "apply_H", "apply_H_adjoint", "apply_H_direct", "apply_H_sparse",
+    "apply_stream_columns", "energy", "build_tables", "dim", "hash_batch",
     "hash_occ", "rho1", "rho2", "t2_lookup", "tables_size", "unhash", "unhash_batch",
     "workspace_size", "zaxpby", "zdotc", "choose_double_jumps", "is_hermitian", "tables_bytes",
 ]

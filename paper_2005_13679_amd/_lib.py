@@ -93,6 +93,8 @@ SIGNATURES = {
     "mc_unhash_batch": (ctypes.c_int, [c_i32, c_i32, ctypes.POINTER(CTables), c_p, c_p, c_i64, c_p]),
     "mc_t2_lookup": (ctypes.c_int, [c_i32, c_i32, ctypes.POINTER(CTables), c_p, c_p, c_i64, c_p]),
     "mc_workspace_size": (ctypes.c_int, [c_i32, c_i32, c_i32, ctypes.POINTER(c_sz)]),
+    "mc_apply_stream_columns": (ctypes.c_int, [c_i32, c_i32, ctypes.POINTER(c_i32),
+                                               ctypes.POINTER(c_i32)]),
     "mc_apply_H": (ctypes.c_int, [c_i32, c_i32, c_p, c_p, ctypes.POINTER(CTables), c_p, c_p,
                                   c_p, c_sz, c_p]),
     "mc_apply_H_adjoint": (ctypes.c_int, [c_i32, c_i32, c_p, c_p, ctypes.POINTER(CTables), c_p,

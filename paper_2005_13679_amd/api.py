@@ -94,6 +94,16 @@ def choose_double_jumps(shapes, budget_bytes: float, form: str = "paper") -> lis
     return [bool(k) for k in keep]
 
 
+def apply_stream_columns(M: int, form: str = "reduced") -> tuple[int, int]:
+    """(jump slots per row, slots a tile whose rows reach every removal pair
+    reads from the tables) of the apply through the double-jump map of
+    `form` ("paper" or "reduced")."""
+    slots, cols = L.c_i32(), L.c_i32()
+    L.check(L.load().mc_apply_stream_columns(M, L.FORMS[form], ctypes.byref(slots),
+                                             ctypes.byref(cols)), "mc_apply_stream_columns")
+    return int(slots.value), int(cols.value)
+
+
 def workspace_size(N: int, M: int, op: int) -> int:
     b = L.c_sz()
     L.check(L.load().mc_workspace_size(N, M, op, ctypes.byref(b)), "mc_workspace_size")

@@ -141,9 +141,12 @@ __host__ __device__ constexpr int pair_s(int M, int p)
 template <int MT>
 constexpr int kSlotBatch = MT * MT < MC_SLOT_BATCH ? MT * MT : MC_SLOT_BATCH;
 // Double-jump blocks of the paper form: a whole M*M block per batch up to
-// M = 5 (fastest measured at M = 5; larger M would spill).
+// M * M = MC_T2_WHOLE_BLOCK (larger M would spill).
+#ifndef MC_T2_WHOLE_BLOCK
+#define MC_T2_WHOLE_BLOCK 25
+#endif
 template <int MT>
-constexpr int kT2Batch = MT * MT <= 25 ? MT * MT : kSlotBatch<MT>;
+constexpr int kT2Batch = MT * MT <= MC_T2_WHOLE_BLOCK ? MT * MT : kSlotBatch<MT>;
 
 // Indices of slots [J0, J0 + SB) of a double-jump block (one per lane).
 template <int MT, int SB, int J0>

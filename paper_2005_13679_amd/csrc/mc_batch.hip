@@ -157,7 +157,7 @@ __device__ __forceinline__ void batch_tile(const BatchInst &I, int64_t tile, con
     const int32_t *t2 = I.t2;
     const double2 *gp = coef + I.gp_off, *hp = coef + I.hp_off;
     if constexpr (KIND == kPaperMap)
-        apply_tile_t2<MT, uint8_t, false>(tile, I.dim, I.cap, sq, occ, t1, pmask, t2_off, t2, hp,
+        apply_tile_paper<MT, uint8_t, false>(tile, I.dim, I.cap, sq, occ, t1, pmask, t2_off, t2, hp,
                                           gp, C, HC);
     else if constexpr (KIND == kPaperChain)
         apply_tile_chained<MT, uint8_t, false>(tile, I.dim, sq, occ, t1, hp, gp, C, HC);
@@ -252,7 +252,7 @@ void k_batch_solo(int N, int nbits, int64_t D, int64_t tiles, int64_t nblocks, i
         xcd_block_as<KIND == kDirect && kDirectRemap<MT>>(blockIdx.x, nblocks) * 4 + wave_in_block();
     if (tile >= tiles) return;
     if constexpr (KIND == kPaperMap)
-        apply_tile_t2<MT, uint8_t, false>(tile, D, cap, sq, occ, t1, pmask, t2_off, t2, hp, gp, C,
+        apply_tile_paper<MT, uint8_t, false>(tile, D, cap, sq, occ, t1, pmask, t2_off, t2, hp, gp, C,
                                           HC);
     else if constexpr (KIND == kPaperChain)
         apply_tile_chained<MT, uint8_t, false>(tile, D, sq, occ, t1, hp, gp, C, HC);

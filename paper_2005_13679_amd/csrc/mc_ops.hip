@@ -137,7 +137,7 @@ void k_apply(int N, int64_t D, int64_t tiles, int64_t nblocks, int64_t cap,
     if constexpr (kLdsRoots<MT>) fill_sqrt_table(sq, N + 3);
     const int64_t tile = xcd_block(blockIdx.x, nblocks) * 4 + wave_in_block();
     if (tile >= tiles) return;
-    apply_tile_t2<MT, OccT, BIGC>(tile, D, cap, sq, occ, t1, pmask, t2_off, t2, h, gp, C, HC);
+    apply_tile_paper<MT, OccT, BIGC>(tile, D, cap, sq, occ, t1, pmask, t2_off, t2, h, gp, C, HC);
 }
 
 template <int MT, typename OccT, bool BIGC>
@@ -678,6 +678,25 @@ int mc_zaxpby(int64_t n, const double *a_d, const double *x_d, const double *b_d
                        (const double2 *)a_d, (const double2 *)x_d, (const double2 *)b_d,
                        (const double2 *)y_d, scale, flags, (double2 *)out_d);
     return launch_status();
+}
+
+int mc_apply_stream_columns(int32_t M, int32_t form, int32_t *slots, int32_t *table_columns)
+{
+    if (!slots || !table_columns || M < 1 || M > 8) return MC_EINVAL;
+    if (form != MC_FORM_PAPER && form != MC_FORM_REDUCED) return MC_EINVAL;
+    const bool paper = form == MC_FORM_PAPER;
+    *slots = M * (M - 1) + (paper ? M * (M + 1) / 2 * M * M
+                                  : M * reduced_slots(M, 0, 0) +
+                                        (M * (M - 1) / 2) * (M >= 2 ? reduced_slots(M, 0, 1) : 0));
+    *table_columns = *slots;
+    switch (M) {
+    case 2: *table_columns = paper ? kClassPlan<2, 1>.anchors : kClassPlan<2, 0>.anchors; break;
+    case 3: *table_columns = paper ? kClassPlan<3, 1>.anchors : kClassPlan<3, 0>.anchors; break;
+    case 4: *table_columns = paper ? kClassPlan<4, 1>.anchors : kClassPlan<4, 0>.anchors; break;
+    case 5: *table_columns = paper ? kClassPlan<5, 1>.anchors : kClassPlan<5, 0>.anchors; break;
+    default: break;
+    }
+    return MC_OK;
 }
 
 int mc_workspace_size(int32_t N, int32_t M, int32_t op, size_t *bytes)

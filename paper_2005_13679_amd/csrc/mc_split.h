@@ -552,83 +552,132 @@ __host__ __device__ constexpr void flat_jump(int U, int &R1, int &R2, int &A1, i
 #endif
 
 // Slot stream of a full tile.  Form 0: the case-split sum (single jumps,
-// then the true double jumps of the reduced map).  (The paper's sum, every
-// slot of every removal pair, walked the same way measured no faster: that
-// kernel is bound by its 111 GB table stream and its register use.)
+// then the true double jumps of the reduced map).  Form 1: the paper's sum
+// (single jumps, then every slot q*M + l of every removal pair, pair-major,
+// as in the paper's double-jump map).
 template <int MT, int FORM>
-struct SlotForm {
-    static_assert(FORM == 0, "class-major stream of the case-split sum only");
+struct SlotForm;
+
+template <int MT>
+struct SlotForm<MT, 0> {
     static constexpr int U = FlatTile<MT>::U;
     static constexpr void jump(int u, int &R1, int &R2, int &A1, int &A2)
     {
         flat_jump<MT>(u, R1, R2, A1, A2);
     }
-    static constexpr int delta(int u, int m)
+};
+
+template <int MT>
+struct SlotForm<MT, 1> {
+    static constexpr int NSING = MT * (MT - 1);
+    static constexpr int U = NSING + MT * (MT + 1) / 2 * MT * MT;
+    static constexpr void jump(int u, int &R1, int &R2, int &A1, int &A2)
     {
-        int R1 = 0, R2 = 0, A1 = 0, A2 = 0;
-        jump(u, R1, R2, A1, A2);
-        return prefix_delta(m, R1, R2, A1, A2);
+        if (u < NSING) {
+            flat_jump<MT>(u, R1, R2, A1, A2);
+            return;
+        }
+        const int e = u - NSING, P = e / (MT * MT), j = e % (MT * MT);
+        R1 = pair_k(MT, P);
+        R2 = pair_s(MT, P);
+        A1 = j / MT;
+        A2 = j % MT;
     }
 };
 
-// The stream in class-major order: position i holds slot slot[i] (-1: the
-// row itself), whose value is the anchor at position anc[i] read from
-// lane + sh[i]; batches of whole classes of at most MC_CLASS_BATCH
-// positions (a larger class is cut into parts, each with an anchor of its
-// own).
+template <int MT, int FORM>
+__host__ __device__ constexpr int slot_delta(int u, int m)
+{
+    int R1 = 0, R2 = 0, A1 = 0, A2 = 0;
+    SlotForm<MT, FORM>::jump(u, R1, R2, A1, A2);
+    return prefix_delta(m, R1, R2, A1, A2);
+}
+
+// The stream in class-major order.  Slots that reach the same configuration
+// (the paper form has many: q <-> l, and slots sharing an orbital, which are
+// single jumps) form one position; its leader is the first such slot, whose
+// removals every other one's include, so the leader is possible wherever
+// any of them is.  Position i: leader slot[i] (-1: the row itself), slots
+// gslot[gstart[i] .. gstart[i+1]) for the arithmetic; its value is the
+// anchor at position anc[i] read from lane + sh[i].  Batches of whole
+// classes of at most MC_CLASS_BATCH positions (a larger class is cut into
+// parts, each with an anchor of its own).
 template <int MT, int FORM>
 struct ClassPlan {
+    static_assert(MT >= 1 && MT <= 5, "class-major stream for M <= 5");
     static constexpr int U = SlotForm<MT, FORM>::U;
-    static constexpr int NP = U + 1;
-    int slot[NP] = {};
-    int anc[NP] = {};
-    int sh[NP] = {};
+    static constexpr int NS = U + 1;   // slots and the row itself
+    static constexpr int NK = 625;   // full keys: 5^(M-1) <= 625
+    int np = 0;
+    int slot[NS] = {};
+    int anc[NS] = {};
+    int sh[NS] = {};
+    int gstart[NS + 1] = {};
+    int gslot[NS] = {};
     int nb = 0;
-    int bstart[NP + 1] = {};
+    int bstart[NS + 1] = {};
     int anchors = 0;
 
     constexpr ClassPlan()
     {
-        // Delta_0 and the class key (Delta_1 .. Delta_{M-2}, base 5) of each slot
-        int d0[NP] = {}, key[NP] = {};
+        // Delta_0, the class key (Delta_1 .. Delta_{M-2}) and the full key
+        // (Delta_0 .. Delta_{M-2}) of each slot, base 5
+        int d0[NS] = {}, ck[NS] = {}, fk[NS] = {};
         for (int v = -1; v < U; ++v) {
-            d0[v + 1] = SlotForm<MT, FORM>::delta(v, 0);
+            d0[v + 1] = slot_delta<MT, FORM>(v, 0);
             int k = 0;
-            for (int m = MT - 2; m >= 1; --m) k = 5 * k + SlotForm<MT, FORM>::delta(v, m) + 2;
-            key[v + 1] = k;
+            for (int m = MT - 2; m >= 1; --m) k = 5 * k + slot_delta<MT, FORM>(v, m) + 2;
+            ck[v + 1] = k;
+            fk[v + 1] = 5 * k + d0[v + 1] + 2;
         }
-        bool used[NP] = {};
-        int pos = 0;
-        for (int a = -1; a < U; ++a) {
-            if (used[a + 1]) continue;
-            // a opens a class: it and every later slot of its class, in parts
-            // of at most MC_CLASS_BATCH
-            int first = pos, part = 0, lead = a;
-            for (int v = a; v < U; ++v) {
-                if (used[v + 1] || key[v + 1] != key[a + 1]) continue;
+        // groups of slots with one target, in slot order
+        int gof_key[NK] = {}, lead[NS] = {}, gof[NS] = {}, ng = 0;
+        for (int k = 0; k < NK; ++k) gof_key[k] = -1;
+        for (int v = -1; v < U; ++v) {
+            int &gk = gof_key[fk[v + 1]];
+            if (gk < 0) {
+                gk = ng;
+                lead[ng] = v;
+                ++ng;
+            }
+            gof[v + 1] = gk;
+        }
+        // classes of groups, cut into parts
+        bool used[NS] = {};
+        int pos = 0, nsl = 0;
+        for (int a = 0; a < ng; ++a) {
+            if (used[a]) continue;
+            int first = pos, part = 0, lg = a;
+            for (int b = a; b < ng; ++b) {
+                if (used[b] || ck[lead[b] + 1] != ck[lead[a] + 1]) continue;
                 if (part == MC_CLASS_BATCH) {
                     first = pos;
                     part = 0;
-                    lead = v;
+                    lg = b;
                 }
-                used[v + 1] = true;
-                slot[pos] = v;
+                used[b] = true;
+                slot[pos] = lead[b];
                 anc[pos] = first;
-                sh[pos] = d0[lead + 1] - d0[v + 1];
-                if (pos == first && v >= 0) ++anchors;
+                sh[pos] = d0[lead[lg] + 1] - d0[lead[b] + 1];
+                if (pos == first && lead[b] >= 0) ++anchors;
+                gstart[pos] = nsl;
+                for (int v = -1; v < U; ++v)
+                    if (gof[v + 1] == b) gslot[nsl++] = v;
                 ++pos;
                 ++part;
             }
         }
+        np = pos;
+        gstart[np] = nsl;
         // greedy batches of whole parts
         int start = 0;
         nb = 0;
         bstart[0] = 0;
-        while (start < NP) {
+        while (start < np) {
             int end = start;
-            while (end < NP) {
+            while (end < np) {
                 int cend = end + 1;
-                while (cend < NP && anc[cend] == anc[end]) ++cend;
+                while (cend < np && anc[cend] == anc[end]) ++cend;
                 if (end > start && cend - start > MC_CLASS_BATCH) break;
                 end = cend;
             }
@@ -655,6 +704,18 @@ __device__ __forceinline__ int32_t lane_shift_i32(int32_t x, int32_t fill)
                                      fill);
 }
 
+// x moved s lanes where the lanes with no source may take any value (DPP
+// with bound control: they read 0, and no fill register is set up).
+template <int S>
+__device__ __forceinline__ int32_t lane_shift_any_i32(int32_t x)
+{
+    if constexpr (S == 0) return x;
+    else if constexpr (S > 0)
+        return lane_shift_any_i32<S - 1>(__builtin_amdgcn_mov_dpp(x, 0x130, 0xF, 0xF, true));
+    else
+        return lane_shift_any_i32<S + 1>(__builtin_amdgcn_mov_dpp(x, 0x138, 0xF, 0xF, true));
+}
+
 template <int S>
 __device__ __forceinline__ double2 lane_shift_c128(double2 v)
 {
@@ -664,7 +725,7 @@ __device__ __forceinline__ double2 lane_shift_c128(double2 v)
         int32_t w[4];
         __builtin_memcpy(w, &v, 16);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) w[k] = lane_shift_i32<S>(w[k], 0);
+        for (int k = 0; k < 4; ++k) w[k] = lane_shift_any_i32<S>(w[k]);
         double2 r;
         __builtin_memcpy(&r, w, 16);
         return r;
@@ -686,6 +747,13 @@ struct ClassConsts<MT, 0> {
     const double (&x)[MT];
 };
 
+// the paper form: h and the pair coefficients G'_{P, q*M+l}
+template <int MT>
+struct ClassConsts<MT, 1> {
+    const double2 *__restrict__ h;
+    const double2 *__restrict__ gp;
+};
+
 
 __device__ __forceinline__ void cmac(double er, double ei, const double2 &c, double &ar, double &ai)
 {
@@ -700,7 +768,33 @@ __device__ __forceinline__ void class_fma(const double2 &c, const RowSq<MT> &R,
                                           const ClassConsts<MT, FORM> &k, double &ar, double &ai)
 {
     constexpr int NSING = MT * (MT - 1);
-    if constexpr (U < 0) {
+    if constexpr (FORM == 1) {
+        if constexpr (U < 0) {
+            return;
+        } else if constexpr (U < NSING) {
+            // h_ab sqrt(n_a (n_b + 1)) C
+            constexpr int a = U / (MT - 1), bb = U % (MT - 1), b = bb + (bb >= a), j = a * MT + b;
+            const double f = R.template root<0>(a) * R.template root<1>(b);
+            cmac(k.h[j].x * f, k.h[j].y * f, c, ar, ai);
+        } else {
+            // A_KS G'_{P,ql} B_ql(m) C with m = n - e_K - e_S; A is zero on
+            // rows that cannot lose (K, S)
+            constexpr int e = U - NSING, P = e / (MT * MT), j = e % (MT * MT);
+            constexpr int q = j / MT, l = j % MT, K = pair_k(MT, P), S = pair_s(MT, P);
+            constexpr int dq = (q == K) + (q == S), dl = (l == K) + (l == S);
+            const double Bf = q == l ? R.template root<1 - dq>(q) * R.template root<2 - dq>(q)
+                                     : R.template root<1 - dq>(q) * R.template root<1 - dl>(l);
+            const double A = R.template root<0>(K) *
+                             (K == S ? R.template root<-1>(K) : R.template root<0>(S));
+            const double w = A * Bf;
+            const double cr = c.x * w, ci = c.y * w;
+            const double2 Gv = k.gp[P * MT * MT + j];
+            ar = fma(Gv.x, cr, ar);
+            ar = fma(-Gv.y, ci, ar);
+            ai = fma(Gv.x, ci, ai);
+            ai = fma(Gv.y, cr, ai);
+        }
+    } else if constexpr (U < 0) {
         return;   // the row itself: its term is added before the stream
     } else if constexpr (U < NSING) {
         constexpr int a = U / (MT - 1), bb = U % (MT - 1), b = bb + (bb >= a), j = a * MT + b;
@@ -730,14 +824,67 @@ __device__ __forceinline__ void class_fma(const double2 &c, const RowSq<MT> &R,
     }
 }
 
+// Whether slot U is a possible jump from occupations n (its removals are
+// there); an impossible jump has a zero amplitude.
+template <int MT, int FORM, int U>
+__device__ __forceinline__ bool slot_valid(const int (&n)[MT])
+{
+    constexpr auto rem = [] {
+        int R1 = 0, R2 = 0, A1 = 0, A2 = 0;
+        SlotForm<MT, FORM>::jump(U, R1, R2, A1, A2);
+        return std::pair<int, int>(R1, R2);
+    }();
+    constexpr int R1 = rem.first, R2 = rem.second;
+    if constexpr (R1 < 0) return true;
+    else if constexpr (R2 < 0) return n[R1] >= 1;
+    else if constexpr (R1 == R2) return n[R1] >= 2;
+    else return n[R1] >= 1 && n[R2] >= 1;
+}
+
+// Run of each lane's row: g + n_0 is the index of the run's last row (the
+// index falls by one per particle moved from orbital 1 to 0 along a run), so
+// two rows share a run exactly when their keys are equal; -1 on rows past
+// the end.  `at[s + kMaxShift]` is the key of lane + s (-1 off the wave).
+constexpr int kMaxShift = 4;
+
+template <int MT>
+struct RunKeys {
+    const int (&n)[MT];
+    int32_t key;
+    int32_t at[2 * kMaxShift + 1];
+};
+
+template <int... Ss>
+__device__ __forceinline__ void run_key_shifts(std::integer_sequence<int, Ss...>, int32_t key,
+                                               int32_t (&at)[2 * kMaxShift + 1])
+{
+    ((at[Ss] = lane_shift_i32<Ss - kMaxShift>(key, -1)), ...);
+}
+
+// The arithmetic of every slot of position I, on its one value.
+template <int MT, int FORM, int I, int... Js>
+__device__ __forceinline__ void group_fma(std::integer_sequence<int, Js...>, const double2 &c,
+                                          const RowSq<MT> &R, const ClassConsts<MT, FORM> &k,
+                                          double &ar, double &ai)
+{
+    constexpr ClassPlan<MT, FORM> cp = kClassPlan<MT, FORM>;
+    (class_fma<MT, FORM, cp.gslot[cp.gstart[I] + Js]>(c, R, k, ar, ai), ...);
+}
+
 // Batch B of the class-major stream (positions [I0, I1)): `tix` holds the
-// batch's target indices (from the source: table loads or closed form).
-// Anchor gathers and the members' edge re-gathers are issued together, then
-// the shifts, then the arithmetic.
-template <int MT, int FORM, bool BIGC, int B, int... Is>
-__device__ __forceinline__ void class_batch(std::integer_sequence<int, Is...>,
+// batch's anchor targets (from the source: table loads or closed form).
+// A member's target is never loaded: on a lane whose row shares its run with
+// the row s lanes on, and where the anchor is possible there, it is the
+// anchor's target at lane + s, so the value moves by a DPP shift; elsewhere
+// (run and tile edges) it is the anchor's target at the lane itself plus s,
+// gathered.  Only where the anchor is impossible at the lane itself (rare)
+// is the member's own target read from the source.  A member impossible at
+// a lane has a zero amplitude there and takes any finite value.
+template <int MT, int FORM, bool BIGC, int B, class Src, int... Is>
+__device__ __forceinline__ void class_batch(std::integer_sequence<int, Is...>, const Src &src,
                                             const int32_t (&tix)[MC_CLASS_BATCH], int32_t own_t,
                                             double2 own_c, const RowSq<MT> &R,
+                                            const RunKeys<MT> &rk,
                                             const ClassConsts<MT, FORM> &k,
                                             const Gather<BIGC> &ldc, double &ar, double &ai)
 {
@@ -754,18 +901,28 @@ __device__ __forceinline__ void class_batch(std::integer_sequence<int, Is...>,
             }
         }(),
         ...);
-    // members: the anchor's index and value from lane + s (DPP wave shifts);
-    // a re-gather on the lanes where that index differs from the member's own
-    bool need[MC_CLASS_BATCH];
+    // members: an edge gather where the shifted anchor does not serve
+    bool edge[MC_CLASS_BATCH], own[MC_CLASS_BATCH];
+    bool any_own = false;
     (
         [&] {
             constexpr int i = I0 + Is;
             if constexpr (i < I1 && cp.anc[i] != i) {
-                constexpr int ai_ = cp.anc[i] - I0;
-                const int32_t at =
-                    lane_shift_i32<cp.sh[i]>(cp.slot[cp.anc[i]] < 0 ? own_t : tix[ai_], -2);
-                need[Is] = at != tix[Is];
-                v[Is] = ldc(need[Is] ? tix[Is] : -1);
+                constexpr int S = cp.sh[i];
+                static_assert(S >= -kMaxShift && S <= kMaxShift, "anchor shift out of range");
+                const int32_t ta = cp.slot[cp.anc[i]] < 0 ? own_t : tix[cp.anc[i] - I0];
+                if constexpr (S == 0) {
+                    // the anchor's own target: only an impossible anchor fails
+                    edge[Is] = slot_valid<MT, FORM, cp.slot[i]>(rk.n) && ta < 0;
+                } else {
+                    // (off the wave the key test already makes the lane an edge)
+                    const int32_t at = lane_shift_any_i32<S>(ta);
+                    edge[Is] = slot_valid<MT, FORM, cp.slot[i]>(rk.n) &&
+                               (rk.at[S + kMaxShift] != rk.key || at < 0);
+                    v[Is] = ldc(edge[Is] && ta >= 0 ? ta + S : -1);
+                }
+                own[Is] = edge[Is] && ta < 0;
+                any_own = any_own || own[Is];
             }
         }(),
         ...);
@@ -773,21 +930,39 @@ __device__ __forceinline__ void class_batch(std::integer_sequence<int, Is...>,
         [&] {
             constexpr int i = I0 + Is;
             if constexpr (i < I1 && cp.anc[i] != i) {
-                const double2 s = lane_shift_c128<cp.sh[i]>(v[cp.anc[i] - I0]);
-                if (!need[Is]) v[Is] = s;
+                if constexpr (cp.sh[i] == 0) {
+                    v[Is] = v[cp.anc[i] - I0];
+                } else {
+                    const double2 sv = lane_shift_c128<cp.sh[i]>(v[cp.anc[i] - I0]);
+                    if (!edge[Is]) v[Is] = sv;
+                }
             }
         }(),
         ...);
+    // wave-uniform and rare: members whose anchor is impossible on the lane
+    if (__builtin_amdgcn_readfirstlane(__ballot(any_own) != 0)) {
+        (
+            [&] {
+                constexpr int i = I0 + Is;
+                if constexpr (i < I1 && cp.anc[i] != i) {
+                    if (own[Is]) v[Is] = ldc(src.template target<cp.slot[i]>());
+                }
+            }(),
+            ...);
+    }
     (
         [&] {
             constexpr int i = I0 + Is;
-            if constexpr (i < I1) class_fma<MT, FORM, cp.slot[i]>(v[Is], R, k, ar, ai);
+            if constexpr (i < I1)
+                group_fma<MT, FORM, i>(
+                    std::make_integer_sequence<int, cp.gstart[i + 1] - cp.gstart[i]>{}, v[Is], R,
+                    k, ar, ai);
         }(),
         ...);
 }
 
-// Target index of class-major position i from the source (the row itself
-// needs none).
+// Target index of the anchors of batch B from the source (the row itself
+// needs none; members are derived).
 template <int MT, int FORM, int B, class Src, int... Is>
 __device__ __forceinline__ void class_targets(std::integer_sequence<int, Is...>, const Src &src,
                                               int32_t (&tix)[MC_CLASS_BATCH])
@@ -797,7 +972,8 @@ __device__ __forceinline__ void class_targets(std::integer_sequence<int, Is...>,
     (
         [&] {
             constexpr int i = I0 + Is;
-            if constexpr (i < I1 && cp.slot[i] >= 0) tix[Is] = src.template target<cp.slot[i]>();
+            if constexpr (i < I1 && cp.slot[i] >= 0 && cp.anc[i] == i)
+                tix[Is] = src.template target<cp.slot[i]>();
         }(),
         ...);
 }
@@ -808,6 +984,7 @@ template <int MT, int FORM, bool BIGC, int B, class Src>
 __device__ __forceinline__ void class_batches(int32_t (&cur)[MC_CLASS_BATCH],
                                               int32_t (&nxt)[MC_CLASS_BATCH], const Src &src,
                                               int32_t own_t, double2 own_c, const RowSq<MT> &R,
+                                              const RunKeys<MT> &rk,
                                               const ClassConsts<MT, FORM> &k,
                                               const Gather<BIGC> &ldc, double &ar, double &ai)
 {
@@ -818,25 +995,31 @@ __device__ __forceinline__ void class_batches(int32_t (&cur)[MC_CLASS_BATCH],
             if constexpr (B + 1 < NB)
                 class_targets<MT, FORM, B + 1>(std::make_integer_sequence<int, MC_CLASS_BATCH>{},
                                                src, nxt);
-            class_batch<MT, FORM, BIGC, B>(std::make_integer_sequence<int, MC_CLASS_BATCH>{}, cur,
-                                           own_t, own_c, R, k, ldc, ar, ai);
+            class_batch<MT, FORM, BIGC, B>(std::make_integer_sequence<int, MC_CLASS_BATCH>{}, src,
+                                           cur, own_t, own_c, R, rk, k, ldc, ar, ai);
         }
-        class_batches<MT, FORM, BIGC, B + 1>(nxt, cur, src, own_t, own_c, R, k, ldc, ar, ai);
+        class_batches<MT, FORM, BIGC, B + 1>(nxt, cur, src, own_t, own_c, R, rk, k, ldc, ar, ai);
     }
 }
 
+// `n`: the row's occupations; own_t: its index (negative past the end).
 template <int MT, int FORM, bool BIGC, class Src>
 __device__ __forceinline__ void class_stream(const Src &src, int32_t own_t, double2 own_c,
-                                             const RowSq<MT> &R, const ClassConsts<MT, FORM> &k,
+                                             const int (&n)[MT], const RowSq<MT> &R,
+                                             const ClassConsts<MT, FORM> &k,
                                              const Gather<BIGC> &ldc, double &ar, double &ai)
 {
+    RunKeys<MT> rk{n, own_t >= 0 ? own_t + n[0] : -1, {}};
+    run_key_shifts(std::make_integer_sequence<int, 2 * kMaxShift + 1>{}, rk.key, rk.at);
     int32_t ta[MC_CLASS_BATCH], tb[MC_CLASS_BATCH];
     class_targets<MT, FORM, 0>(std::make_integer_sequence<int, MC_CLASS_BATCH>{}, src, ta);
-    class_batches<MT, FORM, BIGC, 0>(ta, tb, src, own_t, own_c, R, k, ldc, ar, ai);
+    class_batches<MT, FORM, BIGC, 0>(ta, tb, src, own_t, own_c, R, rk, k, ldc, ar, ai);
 }
 
 // Targets of a full tile through the tables: the tile's single-jump block
-// and its reduced-map block (every pair present, in order).
+// and its double-jump block (every pair present, in order; form 0: the
+// reduced map's true double jumps, form 1: the paper map's M*M slots per
+// pair), column U - M(M-1) of the block either way.
 template <int MT, int FORM>
 struct MapSlots {
     __amdgpu_buffer_rsrc_t r1, r2;
@@ -925,7 +1108,7 @@ __device__ __forceinline__ void apply_tile_split(int64_t tile, int64_t D, int64_
 #if MC_CLASS_STREAM
             const MapSlots<MT, 0> src{r1, r2, lane};
             const ClassConsts<MT, 0> k{HS, GS, GD, x};
-            class_stream<MT, 0, BIGC>(src, live ? (int32_t)g : -2, cg, R, k, ldc, ar, ai);
+            class_stream<MT, 0, BIGC>(src, live ? (int32_t)g : -2, cg, n, R, k, ldc, ar, ai);
 #else
             int32_t ta[FlatTile<MT>::SB], tb[FlatTile<MT>::SB];
             flat_loads<MT, 0>(std::make_integer_sequence<int, FlatTile<MT>::SB>{}, ta, r1, r2, lane);
@@ -988,6 +1171,68 @@ __device__ __forceinline__ void apply_tile_split(int64_t tile, int64_t D, int64_
                                     ldc, ar, ai);
     }
     if (live) HC[g] = make_double2(ar, ai);
+}
+
+// One 64-row tile of H.C in the paper's form (the paper's double-jump map,
+// M*M slots per removal pair).  A full tile (every removal pair present and
+// its whole block in the map), for 2 <= M <= 5, walks the class-major
+// stream: the paper's sum over all its slots, reading only the anchors'
+// table columns and gathering each distinct target once; other tiles take
+// the per-pair path.
+#ifndef MC_PAPER_STREAM
+#define MC_PAPER_STREAM 1
+#endif
+
+template <int MT, typename OccT, bool BIGC>
+__device__ __forceinline__ void apply_tile_paper(int64_t tile, int64_t D, int64_t cap,
+                                                 const double *sq, const OccT *__restrict__ occ,
+                                                 const int32_t *__restrict__ t1,
+                                                 const uint64_t *__restrict__ pmask,
+                                                 const int64_t *__restrict__ t2_off,
+                                                 const int32_t *__restrict__ t2,
+                                                 const double2 *__restrict__ h,
+                                                 const double2 *__restrict__ gp,
+                                                 const double2 *__restrict__ C,
+                                                 double2 *__restrict__ HC)
+{
+    if constexpr (MC_PAPER_STREAM && MT >= 2 && MT <= 5) {
+        constexpr int P = MT * (MT + 1) / 2, W = (P + 63) / 64, NS = MT * MT;
+        int64_t off0, off1;
+        t2_block(t2_off, tile, cap, off0, off1);
+        bool full = off1 - off0 == (int64_t)P * NS * kTile;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const int bits = P - 64 * w < 64 ? P - 64 * w : 64;
+            const uint64_t want = bits == 64 ? ~(uint64_t)0 : (((uint64_t)1 << bits) - 1);
+            full = full && pmask[tile * W + w] == want;
+        }
+        if (full) {
+            const int lane = threadIdx.x & 63;
+            const int64_t g = tile * kTile + lane;
+            const bool live = g < D;
+            int n[MT];
+            RowSq<MT> R;
+            load_row<MT, OccT>(occ, tile, lane, n, R, sq);
+            const Gather<BIGC> ldc(C, D);
+            const double2 cg = ldc(live ? (int32_t)g : -1);
+            // diagonal one-body part: sum_k h_kk n_k C_g
+            double dr = 0.0, di = 0.0;
+#pragma unroll
+            for (int k = 0; k < MT; ++k) {
+                dr = fma(h[k * MT + k].x, (double)n[k], dr);
+                di = fma(h[k * MT + k].y, (double)n[k], di);
+            }
+            double ar = dr * cg.x - di * cg.y, ai = dr * cg.y + di * cg.x;
+            const MapSlots<MT, 1> src{
+                make_rsrc(t1 + tile * NS * kTile, (uint32_t)(NS * kTile * 4)),
+                make_rsrc(t2 + off0, (uint32_t)(P * NS * kTile * 4)), lane};
+            const ClassConsts<MT, 1> k{h, gp};
+            class_stream<MT, 1, BIGC>(src, live ? (int32_t)g : -2, cg, n, R, k, ldc, ar, ai);
+            if (live) HC[g] = make_double2(ar, ai);
+            return;
+        }
+    }
+    apply_tile_t2<MT, OccT, BIGC>(tile, D, cap, sq, occ, t1, pmask, t2_off, t2, h, gp, C, HC);
 }
 
 }  // namespace mc

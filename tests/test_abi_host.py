@@ -260,3 +260,48 @@ def test_tables_bytes_and_double_jump_budget(lib):
     assert lib.mc_choose_double_jumps(1, n, m, 1, 1e9, keep) == -2    # D >= 2^31
     out = ctypes.c_int64()
     assert lib.mc_tables_bytes(10, 5, 7, 1, ctypes.byref(out)) == -1  # unknown form
+
+
+def _class_parts(M, form, batch=16):
+    """Independent count of the class-major stream's parts: jumps grouped by
+    target (equal changes of every prefix sum), targets grouped into classes
+    by their changes of S_1 .. S_{M-2}, the row itself in the class of no
+    change, each class cut into parts of at most `batch` targets."""
+    def delta(rem, add):
+        return tuple(sum(a <= m for a in add) - sum(r <= m for r in rem) for m in range(M - 1))
+    jumps = [((), ())]
+    jumps += [((a,), (b,)) for a in range(M) for b in range(M) if a != b]
+    if form == "reduced":
+        jumps += [((k, s), (q, l)) for k in range(M) for s in range(k, M)
+                  for q in range(M) for l in range(q, M) if q not in (k, s) and l not in (k, s)]
+    else:
+        jumps += [((k, s), (q, l)) for k in range(M) for s in range(k, M)
+                  for q in range(M) for l in range(M)]
+    targets = {delta(rem, add) for rem, add in jumps}
+    sizes = {}
+    for t in targets:
+        sizes[t[1:]] = sizes.get(t[1:], 0) + 1
+    return len(jumps) - 1, len(targets), sum(-(-n // batch) for n in sizes.values())
+
+
+def test_apply_stream_columns(lib):
+    import paper_2005_13679_amd as mc
+    for form in ("reduced", "paper"):
+        for M in range(1, 9):
+            slots, cols = mc.apply_stream_columns(M, form)
+            ref_slots, ntargets, parts = _class_parts(M, form)
+            assert slots == ref_slots
+            if 2 <= M <= 5:
+                # one table column per part, except the part the row itself anchors
+                assert cols == parts - 1
+            else:
+                assert cols == slots
+    # the reduced form's slots all reach distinct configurations
+    assert _class_parts(5, "reduced")[1] == 131 == _class_parts(5, "paper")[1]
+    assert mc.apply_stream_columns(5, "reduced") == (130, 54)
+    assert mc.apply_stream_columns(5, "paper")[0] == 20 + 15 * 25
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    assert lib.mc_apply_stream_columns(0, 1, ctypes.byref(a), ctypes.byref(b)) == -1
+    assert lib.mc_apply_stream_columns(9, 1, ctypes.byref(a), ctypes.byref(b)) == -1
+    assert lib.mc_apply_stream_columns(5, 7, ctypes.byref(a), ctypes.byref(b)) == -1
+    assert lib.mc_apply_stream_columns(5, 1, None, ctypes.byref(b)) == -1
