@@ -129,10 +129,10 @@ def stream_bytes(mc, tab) -> dict:
 # what the counters show limits each path's apply kernel (the HBM roofline is
 # the one that bounds the byte model; these kernels stop short of it)
 LIMITERS = {
-    "reduced_map": "texture data path (99 % busy, 37 % of it waiting on L1 misses of the anchor "
-                   "gathers) and vector ALU (2,800 instructions per tile, about 70 % of the "
+    "reduced_map": "texture data path (98 % busy, 36 % of it waiting on L1 misses of the anchor "
+                   "gathers) and vector ALU (2,550 instructions per tile, about 68 % of the "
                    "cycles): 195 vector memory reads per tile; HBM-side traffic 27.1 GB per apply "
-                   "at 3.3 TB/s (rocprofv3 FETCH_SIZE)",
+                   "at 3.4 TB/s (rocprofv3 FETCH_SIZE)",
     "reduced_chained": "coefficient gathers through L1/TA (chained second hops)",
     "paper_map": "vector ALU (the paper's 395 slots of arithmetic per row on 131 gathered "
                  "targets) and the anchor gathers",
@@ -596,7 +596,8 @@ def main(argv=None):
         # the same apply against structure-once models of whole tables (the
         # kernel reads less; context only, not the roofline)
         "byte_models": {
-            name: {"bytes": b, "equivalent_GB_per_s": b / (ms * 1e-3) / 1e9}
+            name: {"bytes": b, "equivalent_GB_per_s": b / (ms * 1e-3) / 1e9,
+                   "equivalent_frac_of_peak": b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
             for name, b in (("reduced_tables_once", algorithmic_bytes(N, M, "reduced_map")["total"]),
                             ("paper_tables_once", algorithmic_bytes(N, M, "paper_map")["total"]))
         } if has_map else None,

@@ -50,14 +50,20 @@ struct Gather {
 
 // Per-row square roots of small integers used by the jump amplitudes:
 // root<d>(m) = sqrt(n_m + d) for d in {-1, 0, 1, 2} (0 where n_m + d < 0).
-// For M <= 5 the four tables live in registers; for M >= 6 (where they would
-// cost 8M VGPRs) only the occupations do and the roots come from an LDS table
-// of sqrt(i), i = 0 .. N+2, filled once per block.
+// Either the four tables live in registers (8M VGPRs), or only the
+// occupations do and the roots come from an LDS table of sqrt(i),
+// i = 0 .. N+2, filled once per block: from M = 5 on, where the registers
+// are worth more as waves in flight.
 #ifndef MC_LDS_ROOTS_FROM
-#define MC_LDS_ROOTS_FROM 6
+#define MC_LDS_ROOTS_FROM 5
 #endif
 template <int MT>
 constexpr bool kLdsRoots = MT >= MC_LDS_ROOTS_FROM;
+// The chained paper-form body keeps its roots in registers up to M = 5
+// (measured: the LDS table slowed it by a fifth at M = 5, while it sped the
+// map and case-split bodies up by 2-6 %, their registers going to waves).
+template <int MT>
+constexpr bool kLdsRootsChained = MT >= 6;
 
 template <int MT, bool LDS = kLdsRoots<MT>>
 struct RowSq;
@@ -109,9 +115,9 @@ __device__ __forceinline__ void fill_sqrt_table(double *tab, int n)
     __syncthreads();
 }
 
-template <int MT, typename OccT>
+template <int MT, typename OccT, bool LDS>
 __device__ __forceinline__ void load_row(const OccT *__restrict__ occ, int64_t tile, int lane,
-                                         int (&n)[MT], RowSq<MT> &R, const double *sq)
+                                         int (&n)[MT], RowSq<MT, LDS> &R, const double *sq)
 {
 #pragma unroll
     for (int m = 0; m < MT; ++m) n[m] = (int)occ[(tile * MT + m) * kTile + lane];
@@ -386,7 +392,7 @@ __device__ __forceinline__ void apply_tile_t2(int64_t tile, int64_t D, int64_t c
 template <int MT, bool BIGC, int P>
 __device__ __forceinline__ void pair_term_chained(int64_t D, const int32_t *__restrict__ t1,
                                                   __amdgpu_buffer_rsrc_t r1, int lane,
-                                                  const int (&n)[MT], const RowSq<MT> &R,
+                                                  const int (&n)[MT], const RowSq<MT, kLdsRootsChained<MT>> &R,
                                                   const double2 *__restrict__ gp,
                                                   const Gather<BIGC> &ldc, double &ar, double &ai)
 {
@@ -543,7 +549,7 @@ template <int MT, bool BIGC, int... Ps>
 __device__ __forceinline__ void all_pairs_chained(std::integer_sequence<int, Ps...>, int64_t D,
                                                   const int32_t *__restrict__ t1,
                                                   __amdgpu_buffer_rsrc_t r1, int lane,
-                                                  const int (&n)[MT], const RowSq<MT> &R,
+                                                  const int (&n)[MT], const RowSq<MT, kLdsRootsChained<MT>> &R,
                                                   const double2 *__restrict__ gp,
                                                   const Gather<BIGC> &ldc, double &ar, double &ai)
 {
@@ -567,7 +573,7 @@ __device__ __forceinline__ void apply_tile_chained(int64_t tile, int64_t D, cons
     const int64_t g = tile * kTile + lane;
     const bool live = g < D;
     int n[M];
-    RowSq<M> R;
+    RowSq<M, kLdsRootsChained<MT>> R;
     load_row<MT, OccT>(occ, tile, lane, n, R, sq);
     const Gather<BIGC> ldc(C, D);
     const __amdgpu_buffer_rsrc_t r1 =
@@ -615,7 +621,7 @@ __device__ __forceinline__ void apply_tile_chained(int64_t tile, int64_t D, cons
             ai = fma(hv.y, cr, ai);
         }
     }
-    if constexpr (kLdsRoots<MT>)
+    if constexpr (kLdsRootsChained<MT>)
         pairs_chained_loop<MT, BIGC>(D, g, t1, r1, lane, n, sq, gp, ldc, ar, ai);
     else
         all_pairs_chained<MT, BIGC>(std::make_integer_sequence<int, P>{}, D, t1, r1, lane, n, R, gp,
