@@ -252,12 +252,12 @@ int mc_workspace_size(int32_t N, int32_t M, int32_t op, size_t *bytes);
  * particle moved between orbitals 0 and 1, Eq. TotalCost) a jump's target is
  * the row's index plus a constant of the run and of the jump's class (the
  * jumps that change the prefix sums S_1 .. S_{M-2} alike), so on a tile where
- * every removal pair occurs (2 <= M <= 5) the kernel reads from the tables
+ * every removal pair occurs (2 <= M <= 6) the kernel reads from the tables
  * only one jump per class and derives the others' targets; slots with one
  * target share one coefficient.  form: MC_FORM_PAPER (single jumps and the
  * M*M slots of every removal pair) or MC_FORM_REDUCED (single jumps and the
  * true double jumps).  *slots: jump slots per row; *table_columns: those
- * read from the tables per such tile.  M outside 2..5: every slot is read
+ * read from the tables per such tile.  M outside 2..6: every slot is read
  * (*table_columns = *slots).  MC_EINVAL for M outside 1..8, an unknown form
  * or NULL outputs. */
 int mc_apply_stream_columns(int32_t M, int32_t form, int32_t *slots, int32_t *table_columns);
@@ -296,7 +296,7 @@ int mc_apply_H_sparse(int32_t N, int32_t M, const double *h_d, const double *g_d
  * differences (the O(M) index delta; Sec. III, IV).  Needs no mc_tables:
  * device memory is C_d, HC_d and the workspace only, which lifts the table
  * memory limit on N.  1 <= M <= 8 and D < 2^31 (else MC_EINVAL / MC_ERANGE),
- * (N+3)*8 <= 65536 for M >= 6 (an LDS table of square roots; M <= 5 keeps
+ * (N+3)*8 <= 65536 for M >= 5 (an LDS table of square roots; M <= 4 keeps
  * them in registers); ws_d: mc_workspace_size(APPLY) bytes (staged constants,
  * so concurrent calls need separate ws); HC_d must not overlap C_d.  The
  * terms and their order are those of mc_apply_H on reduced-form tables, so

@@ -694,6 +694,10 @@ int mc_apply_stream_columns(int32_t M, int32_t form, int32_t *slots, int32_t *ta
     case 3: *table_columns = paper ? kClassPlan<3, 1>.anchors : kClassPlan<3, 0>.anchors; break;
     case 4: *table_columns = paper ? kClassPlan<4, 1>.anchors : kClassPlan<4, 0>.anchors; break;
     case 5: *table_columns = paper ? kClassPlan<5, 1>.anchors : kClassPlan<5, 0>.anchors; break;
+    case 6:
+        if (kStreamMaxM >= 6)
+            *table_columns = paper ? kClassPlan<6, 1>.anchors : kClassPlan<6, 0>.anchors;
+        break;
     default: break;
     }
     return MC_OK;
@@ -786,7 +790,7 @@ static int apply_common(int32_t N, int32_t M, const double *h_d, const double *g
                        (const double2 *)h_d, gp, hp);
     const int64_t nblocks = (t->tiles + 3) / 4;
     const bool big = D * 16 > (int64_t)0xFFFFFFFFu;
-    const size_t sqb = (size_t)(N + 3) * 8;   // sqrt table for M >= 6
+    const size_t sqb = (size_t)(N + 3) * 8;   // LDS square-root table (kLdsRoots)
     if (sqb > 65536) return MC_EINVAL;
     // Instantiated combinations: 16-bit occupations only for M <= 5 (M >= 6
     // with N > 255 has D > 2^31), 64-bit gathers (D >= 2^28) only without the

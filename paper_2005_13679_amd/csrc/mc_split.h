@@ -547,6 +547,11 @@ __host__ __device__ constexpr void flat_jump(int U, int &R1, int &R2, int &A1, i
 #ifndef MC_CLASS_STREAM
 #define MC_CLASS_STREAM 1
 #endif
+// largest orbital count whose full tiles take the class-major stream
+#ifndef MC_STREAM_MAX_M
+#define MC_STREAM_MAX_M 6
+#endif
+constexpr int kStreamMaxM = MC_STREAM_MAX_M;
 #ifndef MC_CLASS_BATCH
 #define MC_CLASS_BATCH 16
 #endif
@@ -604,10 +609,10 @@ __host__ __device__ constexpr int slot_delta(int u, int m)
 // parts, each with an anchor of its own).
 template <int MT, int FORM>
 struct ClassPlan {
-    static_assert(MT >= 1 && MT <= 5, "class-major stream for M <= 5");
+    static_assert(MT >= 1 && MT <= 6, "class-major stream for M <= 6");
     static constexpr int U = SlotForm<MT, FORM>::U;
     static constexpr int NS = U + 1;   // slots and the row itself
-    static constexpr int NK = 625;   // full keys: 5^(M-1) <= 625
+    static constexpr int NK = 3125;   // full keys: 5^(M-1) <= 3125
     int np = 0;
     int slot[NS] = {};
     int anc[NS] = {};
@@ -644,7 +649,8 @@ struct ClassPlan {
         }
         // classes of groups, cut into parts
         bool used[NS] = {};
-        int pos = 0, nsl = 0;
+        int posg[NS] = {}, cnt[NS] = {};
+        int pos = 0;
         for (int a = 0; a < ng; ++a) {
             if (used[a]) continue;
             int first = pos, part = 0, lg = a;
@@ -660,15 +666,21 @@ struct ClassPlan {
                 anc[pos] = first;
                 sh[pos] = d0[lead[lg] + 1] - d0[lead[b] + 1];
                 if (pos == first && lead[b] >= 0) ++anchors;
-                gstart[pos] = nsl;
-                for (int v = -1; v < U; ++v)
-                    if (gof[v + 1] == b) gslot[nsl++] = v;
+                posg[b] = pos;
                 ++pos;
                 ++part;
             }
         }
         np = pos;
-        gstart[np] = nsl;
+        // each position's slots, in slot order
+        for (int v = -1; v < U; ++v) ++cnt[posg[gof[v + 1]]];
+        gstart[0] = 0;
+        for (int i = 0; i < np; ++i) gstart[i + 1] = gstart[i] + cnt[i];
+        int fill[NS] = {};
+        for (int v = -1; v < U; ++v) {
+            const int i = posg[gof[v + 1]];
+            gslot[gstart[i] + fill[i]++] = v;
+        }
         // greedy batches of whole parts
         int start = 0;
         nb = 0;
@@ -1091,7 +1103,7 @@ __device__ __forceinline__ void apply_tile_split(int64_t tile, int64_t D, int64_
     }
 
     const __amdgpu_buffer_rsrc_t r1 = make_rsrc(t1 + tile * NS * kTile, (uint32_t)(NS * kTile * 4));
-    if constexpr (MAP && MT <= 5 && FlatTile<MT>::NDBL > 0) {
+    if constexpr (MAP && MT <= kStreamMaxM && FlatTile<MT>::NDBL > 0) {
         // every pair present and the block exactly the full size: one stream
         int64_t off0, off1;
         t2_block(t2_off, tile, cap, off0, off1);
@@ -1175,7 +1187,7 @@ __device__ __forceinline__ void apply_tile_split(int64_t tile, int64_t D, int64_
 
 // One 64-row tile of H.C in the paper's form (the paper's double-jump map,
 // M*M slots per removal pair).  A full tile (every removal pair present and
-// its whole block in the map), for 2 <= M <= 5, walks the class-major
+// its whole block in the map), for 2 <= M <= 6, walks the class-major
 // stream: the paper's sum over all its slots, reading only the anchors'
 // table columns and gathering each distinct target once; other tiles take
 // the per-pair path.
@@ -1195,7 +1207,7 @@ __device__ __forceinline__ void apply_tile_paper(int64_t tile, int64_t D, int64_
                                                  const double2 *__restrict__ C,
                                                  double2 *__restrict__ HC)
 {
-    if constexpr (MC_PAPER_STREAM && MT >= 2 && MT <= 5) {
+    if constexpr (MC_PAPER_STREAM && MT >= 2 && MT <= kStreamMaxM) {
         constexpr int P = MT * (MT + 1) / 2, W = (P + 63) / 64, NS = MT * MT;
         int64_t off0, off1;
         t2_block(t2_off, tile, cap, off0, off1);

@@ -291,7 +291,7 @@ def test_apply_stream_columns(lib):
             slots, cols = mc.apply_stream_columns(M, form)
             ref_slots, ntargets, parts = _class_parts(M, form)
             assert slots == ref_slots
-            if 2 <= M <= 5:
+            if 2 <= M <= 6:
                 # one table column per part, except the part the row itself anchors
                 assert cols == parts - 1
             else:
