@@ -257,7 +257,7 @@ int mc_workspace_size(int32_t N, int32_t M, int32_t op, size_t *bytes);
  * target share one coefficient.  form: MC_FORM_PAPER (single jumps and the
  * M*M slots of every removal pair) or MC_FORM_REDUCED (single jumps and the
  * true double jumps).  *slots: jump slots per row; *table_columns: those
- * read from the tables per such tile.  M outside 2..6: every slot is read
+ * read from the tables per such tile.  Larger M: every slot is read
  * (*table_columns = *slots).  MC_EINVAL for M outside 1..8, an unknown form
  * or NULL outputs. */
 int mc_apply_stream_columns(int32_t M, int32_t form, int32_t *slots, int32_t *table_columns);

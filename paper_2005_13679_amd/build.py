@@ -32,6 +32,9 @@ FLAGS = [
     "-Wno-cuda-compat",
     # packed FP32 instructions are disabled for all device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # the compile-time stream plans (up to M = 7) take more constant-
+    # evaluation steps than the default allows
+    "-fconstexpr-steps=33554432",
     f"-I{INCLUDE}",
     f"-I{CSRC}",
 ]

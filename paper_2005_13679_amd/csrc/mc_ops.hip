@@ -695,8 +695,11 @@ int mc_apply_stream_columns(int32_t M, int32_t form, int32_t *slots, int32_t *ta
     case 4: *table_columns = paper ? kClassPlan<4, 1>.anchors : kClassPlan<4, 0>.anchors; break;
     case 5: *table_columns = paper ? kClassPlan<5, 1>.anchors : kClassPlan<5, 0>.anchors; break;
     case 6:
-        if (kStreamMaxM >= 6)
+        if (paper ? kStreamMaxMPaper >= 6 : kStreamMaxMReduced >= 6)
             *table_columns = paper ? kClassPlan<6, 1>.anchors : kClassPlan<6, 0>.anchors;
+        break;
+    case 7:
+        if (!paper && kStreamMaxMReduced >= 7) *table_columns = kClassPlan<7, 0>.anchors;
         break;
     default: break;
     }

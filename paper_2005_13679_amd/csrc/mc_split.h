@@ -502,18 +502,18 @@ __device__ __forceinline__ void flat_batches(int32_t (&cur)[FlatTile<MT>::SB],
 //
 // Consecutive rows of a run (indices that differ by one particle moved
 // between orbitals 0 and 1) share the prefix sums S_1 .. S_{M-1} (mc_direct.h
-// has the closed form of the index), so a jump that changes S_m by Delta_m
-// reaches index  g - Delta_0 + K,  where K depends only on the run and on
+// has the closed form of the index, in which only G_0(S_0) = S_0 + 1 moves
+// along a run), so a jump that changes S_m by Delta_m reaches index
+// g - Delta_0 + K, where K depends only on the run and on
 // (Delta_1 .. Delta_{M-2}).  Jumps with equal (Delta_1 .. Delta_{M-2}) form a
-// class: slot U needs at lane i the coefficient its class's anchor reads at
-// lane i + s, s = Delta_0(anchor) - Delta_0(U), whenever both lanes hold rows
-// of one run.  Each class gathers once (the anchor) and its other slots take
-// the anchor's value from lane i + s (DPP wave shifts), re-gathering only on
-// the lanes where the shifted anchor index differs from their own (run and
-// tile edges): equal indices give equal values, so the result never depends
-// on the run structure, only the gather count does.  The row's own
-// coefficient anchors the class of jumps within orbitals {0, 1}.  M = 5:
-// 130 slots, 54 anchors.
+// class; with s = Delta_0(anchor) - Delta_0(U), slot U's target at row g is
+// its anchor's target at row g + s (same run) and equally the anchor's
+// target at row g plus s.  So only the anchors' targets are read from the
+// source; a member takes the anchor's value from lane i + s (DPP wave
+// shifts) where lane i + s holds a row of the same run and the anchor is
+// possible there, and is gathered at the anchor's own target plus s on the
+// other lanes (run and tile edges).  The row's own coefficient anchors the
+// class of jumps within orbitals {0, 1}.  M = 5: 130 slots, 54 anchors.
 // ---------------------------------------------------------------------------
 
 // Change of S_m when particles leave R1, R2 and enter A1, A2 (-1: none).
@@ -547,11 +547,18 @@ __host__ __device__ constexpr void flat_jump(int U, int &R1, int &R2, int &A1, i
 #ifndef MC_CLASS_STREAM
 #define MC_CLASS_STREAM 1
 #endif
-// largest orbital count whose full tiles take the class-major stream
-#ifndef MC_STREAM_MAX_M
-#define MC_STREAM_MAX_M 6
+// largest orbital count whose full tiles take the class-major stream, per
+// form (the paper form's slots grow as M^4: 786 at M = 6, 1414 at M = 7;
+// the reduced form's stream at M = 7 measured slower than its per-pair path,
+// at 205 VGPRs)
+#ifndef MC_STREAM_MAX_M_REDUCED
+#define MC_STREAM_MAX_M_REDUCED 6
 #endif
-constexpr int kStreamMaxM = MC_STREAM_MAX_M;
+#ifndef MC_STREAM_MAX_M_PAPER
+#define MC_STREAM_MAX_M_PAPER 6
+#endif
+constexpr int kStreamMaxMReduced = MC_STREAM_MAX_M_REDUCED;
+constexpr int kStreamMaxMPaper = MC_STREAM_MAX_M_PAPER;
 #ifndef MC_CLASS_BATCH
 #define MC_CLASS_BATCH 16
 #endif
@@ -609,10 +616,10 @@ __host__ __device__ constexpr int slot_delta(int u, int m)
 // parts, each with an anchor of its own).
 template <int MT, int FORM>
 struct ClassPlan {
-    static_assert(MT >= 1 && MT <= 6, "class-major stream for M <= 6");
+    static_assert(MT >= 1 && MT <= 7, "class-major stream for M <= 7");
     static constexpr int U = SlotForm<MT, FORM>::U;
     static constexpr int NS = U + 1;   // slots and the row itself
-    static constexpr int NK = 3125;   // full keys: 5^(M-1) <= 3125
+    static constexpr int NK = 15625;   // full keys: 5^(M-1) <= 15625
     int np = 0;
     int slot[NS] = {};
     int anc[NS] = {};
@@ -1103,7 +1110,7 @@ __device__ __forceinline__ void apply_tile_split(int64_t tile, int64_t D, int64_
     }
 
     const __amdgpu_buffer_rsrc_t r1 = make_rsrc(t1 + tile * NS * kTile, (uint32_t)(NS * kTile * 4));
-    if constexpr (MAP && MT <= kStreamMaxM && FlatTile<MT>::NDBL > 0) {
+    if constexpr (MAP && MT <= kStreamMaxMReduced && FlatTile<MT>::NDBL > 0) {
         // every pair present and the block exactly the full size: one stream
         int64_t off0, off1;
         t2_block(t2_off, tile, cap, off0, off1);
@@ -1187,7 +1194,7 @@ __device__ __forceinline__ void apply_tile_split(int64_t tile, int64_t D, int64_
 
 // One 64-row tile of H.C in the paper's form (the paper's double-jump map,
 // M*M slots per removal pair).  A full tile (every removal pair present and
-// its whole block in the map), for 2 <= M <= 6, walks the class-major
+// its whole block in the map), for 2 <= M <= kStreamMaxMPaper, walks the class-major
 // stream: the paper's sum over all its slots, reading only the anchors'
 // table columns and gathering each distinct target once; other tiles take
 // the per-pair path.
@@ -1207,7 +1214,7 @@ __device__ __forceinline__ void apply_tile_paper(int64_t tile, int64_t D, int64_
                                                  const double2 *__restrict__ C,
                                                  double2 *__restrict__ HC)
 {
-    if constexpr (MC_PAPER_STREAM && MT >= 2 && MT <= kStreamMaxM) {
+    if constexpr (MC_PAPER_STREAM && MT >= 2 && MT <= kStreamMaxMPaper) {
         constexpr int P = MT * (MT + 1) / 2, W = (P + 63) / 64, NS = MT * MT;
         int64_t off0, off1;
         t2_block(t2_off, tile, cap, off0, off1);
