@@ -881,13 +881,60 @@ __device__ __forceinline__ void run_key_shifts(std::integer_sequence<int, Ss...>
 }
 
 // The arithmetic of every slot of position I, on its one value.
+// Complex coefficient of paper-form slot U (U >= 0) on this row, added to
+// (er, ei): the single jump's h_ab sqrt(n_a (n_b + 1)), or the double jump's
+// A_KS B_ql(m) G'_{P,ql}.
+template <int MT, int U>
+__device__ __forceinline__ void paper_coef(const RowSq<MT> &R, const ClassConsts<MT, 1> &k,
+                                           double &er, double &ei)
+{
+    constexpr int NSING = MT * (MT - 1);
+    if constexpr (U < NSING) {
+        constexpr int a = U / (MT - 1), bb = U % (MT - 1), b = bb + (bb >= a), j = a * MT + b;
+        const double f = R.template root<0>(a) * R.template root<1>(b);
+        er = fma(k.h[j].x, f, er);
+        ei = fma(k.h[j].y, f, ei);
+    } else {
+        constexpr int e = U - NSING, P = e / (MT * MT), j = e % (MT * MT);
+        constexpr int q = j / MT, l = j % MT, K = pair_k(MT, P), S = pair_s(MT, P);
+        constexpr int dq = (q == K) + (q == S), dl = (l == K) + (l == S);
+        const double Bf = q == l ? R.template root<1 - dq>(q) * R.template root<2 - dq>(q)
+                                 : R.template root<1 - dq>(q) * R.template root<1 - dl>(l);
+        const double A = R.template root<0>(K) *
+                         (K == S ? R.template root<-1>(K) : R.template root<0>(S));
+        const double w = A * Bf;
+        const double2 Gv = k.gp[P * MT * MT + j];
+        er = fma(Gv.x, w, er);
+        ei = fma(Gv.y, w, ei);
+    }
+}
+
+// The arithmetic of every slot of position I, on its one value.  Slots that
+// share the value (the paper form's q <-> l and coincident slots) add their
+// coefficients first and multiply the value once.
 template <int MT, int FORM, int I, int... Js>
 __device__ __forceinline__ void group_fma(std::integer_sequence<int, Js...>, const double2 &c,
                                           const RowSq<MT> &R, const ClassConsts<MT, FORM> &k,
                                           double &ar, double &ai)
 {
     constexpr ClassPlan<MT, FORM> cp = kClassPlan<MT, FORM>;
-    (class_fma<MT, FORM, cp.gslot[cp.gstart[I] + Js]>(c, R, k, ar, ai), ...);
+    constexpr int n0 = cp.gstart[I];
+    constexpr int ns = sizeof...(Js);
+    if constexpr (FORM == 1 && ns > 1) {
+        // the row itself (slot -1) carries no coefficient of its own
+        constexpr int first = cp.gslot[n0] < 0 ? 1 : 0;
+        if constexpr (ns - first > 1) {
+            double er = 0.0, ei = 0.0;
+            (
+                [&] {
+                    if constexpr (Js >= first) paper_coef<MT, cp.gslot[n0 + Js]>(R, k, er, ei);
+                }(),
+                ...);
+            cmac(er, ei, c, ar, ai);
+            return;
+        }
+    }
+    (class_fma<MT, FORM, cp.gslot[n0 + Js]>(c, R, k, ar, ai), ...);
 }
 
 // Batch B of the class-major stream (positions [I0, I1)): `tix` holds the
