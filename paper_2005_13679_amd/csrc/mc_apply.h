@@ -154,14 +154,35 @@ constexpr int kSlotBatch = MT * MT < MC_SLOT_BATCH ? MT * MT : MC_SLOT_BATCH;
 template <int MT>
 constexpr int kT2Batch = MT * MT <= MC_T2_WHOLE_BLOCK ? MT * MT : kSlotBatch<MT>;
 
-// Indices of slots [J0, J0 + SB) of a double-jump block (one per lane).
+// The paper's double-jump block holds one column per ordered creation pair
+// (q, l); (q, l) and (l, q) reach one configuration, so the per-pair walk
+// reads the columns with q <= l only and weights them by G'_{P,ql} +
+// G'_{P,lq}.  Slot j of the walk is column t2_col(j) of the block.
+#ifndef MC_PAPER_TRIANGLE
+#define MC_PAPER_TRIANGLE 1
+#endif
+template <int MT>
+constexpr int kT2Slots = MC_PAPER_TRIANGLE ? MT * (MT + 1) / 2 : MT * MT;
+
+template <int MT>
+__host__ __device__ constexpr int t2_col(int j)
+{
+    if (!MC_PAPER_TRIANGLE) return j;
+    for (int q = 0; q < MT; ++q) {
+        if (j < MT - q) return q * MT + q + j;
+        j -= MT - q;
+    }
+    return 0;
+}
+
+// Indices of walk slots [J0, J0 + SB) of a double-jump block (one per lane).
 template <int MT, int SB, int J0>
 __device__ __forceinline__ void load_t2_batch(int32_t (&t)[SB], __amdgpu_buffer_rsrc_t r, int lane)
 {
-    constexpr int NS = MT * MT;
 #pragma unroll
     for (int i = 0; i < SB; ++i)
-        if (J0 + i < NS) t[i] = buf_ld_i32(r, (uint32_t)(((J0 + i) * kTile + lane) * 4), 0);
+        if (J0 + i < kT2Slots<MT>)
+            t[i] = buf_ld_i32(r, (uint32_t)((t2_col<MT>(J0 + i) * kTile + lane) * 4), 0);
 }
 
 // Resource over the double-jump block starting at `pos`, clipped to the
@@ -193,7 +214,7 @@ __device__ __forceinline__ void pair_batches(const int32_t *t2, int64_t pos, int
                                              const Gather<BIGC> &ldc, double &br, double &bi)
 {
     if constexpr (B < NB) {
-        constexpr int NS = MT * MT, SB = kT2Batch<MT>, J0 = B * SB;
+        constexpr int NS = kT2Slots<MT>, SB = kT2Batch<MT>, J0 = B * SB;
         double2 c[SB];
         if constexpr (MC_T2_PIPELINE == 0) {
             // indices of this batch, then its gathers
@@ -209,7 +230,8 @@ __device__ __forceinline__ void pair_batches(const int32_t *t2, int64_t pos, int
             if constexpr (B + 1 < NB) {
                 load_t2_batch<MT, SB, J0 + SB>(tn, r2, lane);
             } else if constexpr (MC_T2_PIPELINE == 2) {
-                const __amdgpu_buffer_rsrc_t rn = t2_block_rsrc(t2, pos + NS * kTile, off1, NS);
+                const __amdgpu_buffer_rsrc_t rn =
+                    t2_block_rsrc(t2, pos + MT * MT * kTile, off1, MT * MT);
                 load_t2_batch<MT, SB, 0>(tf, rn, lane);
             }
         }
@@ -217,10 +239,14 @@ __device__ __forceinline__ void pair_batches(const int32_t *t2, int64_t pos, int
         for (int i = 0; i < SB; ++i) {
             const int j = J0 + i;
             if (j >= NS) break;
-            const int q = j / MT, l = j % MT;
+            const int col = t2_col<MT>(j), q = col / MT, l = col % MT;
             const double Bf = q == l ? rq[q] * dq[q] : rq[q] * rq[l];
             const double cr = c[i].x * Bf, ci = c[i].y * Bf;
-            const double2 Gv = G[j];
+            double2 Gv = G[col];
+            if (MC_PAPER_TRIANGLE && q != l) {
+                Gv.x += G[l * MT + q].x;
+                Gv.y += G[l * MT + q].y;
+            }
             br = fma(Gv.x, cr, br);
             br = fma(-Gv.y, ci, br);
             bi = fma(Gv.x, ci, bi);
@@ -238,7 +264,7 @@ __device__ __forceinline__ void pair_term(const int32_t *t2, int64_t pos, int64_
 {
     constexpr int K = pair_k(MT, P), S = pair_s(MT, P);
     constexpr int NS = MT * MT, SB = kT2Batch<MT>;
-    constexpr int NB = (NS + SB - 1) / SB;
+    constexpr int NB = (kT2Slots<MT> + SB - 1) / SB;
     const __amdgpu_buffer_rsrc_t r2 = make_rsrc(t2 + pos, (uint32_t)(NS * kTile * 4));
     const bool valid = K == S ? n[K] >= 2 : (n[K] >= 1 && n[S] >= 1);
     const double A =
